@@ -1,0 +1,141 @@
+/*
+ * bec.h -- C ABI of the MI355X (gfx950) PCG-ATKM ground-state library.
+ *
+ * Problem (paper Sec. 1, eqs. "DipGPE0", "Vpoten", "DDI-3D", "energy", "groundDef"):
+ * minimise the discrete energy
+ *   E(phi) = < -1/2 [[Lap]]phi + V phi + beta/2 |phi|^2 phi + lambda/2 Phi phi - Omega [[L_z]]phi, phi >
+ * over the unit sphere ||phi|| = 1 (Sec. 2.3, eq. "mp"), with V the harmonic trap, Phi the dipolar
+ * potential U_dip * |phi|^2 evaluated by the anisotropic truncated kernel method (Sec. 2.2), and
+ * the Riemannian preconditioned conjugate gradient of Algorithm 1 (PCG-ATKM, Sec. 2.3).
+ *
+ * Conventions shared by every entry point:
+ *  - Grid: box prod_a [-a_a, a_a) with N_a even points, x_j = -a + j h, h = 2a/N (Sec. 2.1).
+ *  - Fields: contiguous C order [Nx][Ny][Nz], z fastest. Complex fields are interleaved
+ *    (re, im): complex128 (double2) on BEC_FP64 grids, complex64 (float2) on BEC_FP32 grids.
+ *    Real fields (Phi) are double / float accordingly. All field pointers are device pointers.
+ *  - Inner product <u, v> = Re(h_x h_y h_z sum u conj(v)) (eq. "innerPro"); ||.||_inf unweighted.
+ *  - Ownership: the caller owns every device buffer and the workspace (it asks
+ *    bec_workspace_bytes for the size and allocates it). The handle holds host metadata and
+ *    views into the workspace; the library never allocates or frees device memory except in
+ *    bec_init_grid for a few KB of twiddle/quadrature tables, released by bec_destroy_grid.
+ *  - Streams: all work is enqueued on the stream given to bec_init_grid (a hipStream_t, or
+ *    NULL for the default stream) and is asynchronous, except calls that return host data
+ *    (bec_energy with out_on_host, bec_pcg_solve), which synchronise that stream.
+ *    A handle must not be used from two threads at once.
+ *  - Errors: arguments are validated before any launch; nothing throws or aborts. A HIP
+ *    failure marks the handle (BEC_EHIP) and every later call on it returns BEC_EHIP.
+ *    bec_last_error() gives a thread-local message for the last failing call.
+ */
+#ifndef BEC_H
+#define BEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BEC_OK = 0,
+    BEC_EINVAL = -1,    /* bad argument (odd/too small N, a <= 0, |n| != 1, NULL, ...) */
+    BEC_ENOMEM = -2,    /* workspace too small */
+    BEC_EHIP = -3,      /* HIP runtime error; the handle is unusable afterwards */
+    BEC_ENOTCONV = -4,  /* max_iter reached; phi and the result are still written */
+    BEC_ENUMERIC = -5,  /* NaN/Inf met; phi is rolled back to the last accepted iterate */
+    BEC_ESTALL = -6     /* reserved */
+};
+
+typedef enum { BEC_FP64 = 0, BEC_FP32 = 1 } bec_precision;
+
+/* Box and grid (Sec. 2.1): N_a even, 4 <= N_a <= 2048, each N_a = 2^i 3^j 5^k. */
+typedef struct { int32_t n[3]; double a[3]; } bec_grid_desc;
+
+/* Physical parameters (eqs. "DipGPE0", "Vpoten", "DDI-3D"): trap frequencies gamma, contact
+ * strength beta, dipolar strength lambda, dipole axis n (unit; normalised if within 1e-12),
+ * rotation speed Omega. */
+typedef struct { double gamma[3]; double beta, lambda; double n[3]; double omega; } bec_params;
+
+/* Energy parts (Sec. 3: E_kin, E_pot, E_int, E_dip, E_rot), chemical potential
+ * mu = <H phi, phi> (eq. "EL"), mass h^3 sum |phi|^2 and virial residual
+ * 2 E_kin - 2 E_pot + 3 E_int + 3 E_dip (eq. "vir_iden"). */
+typedef struct { double E, Ekin, Epot, Eint, Edip, Erot, mu, mass, virial; } bec_energies;
+
+/* Options of Algorithm 1. */
+typedef struct {
+    double tol_res_inf;    /* stop when ||H phi - mu phi||_inf <= tol (default 1e-8)          */
+    double tol_step_inf;   /* 0 = off; the paper's rule ||phi_{n+1} - phi_n||_inf <= tol       */
+    int32_t max_iter;      /* default 20000                                                   */
+    int32_t max_halvings;  /* step halvings before a forced accept (default 30)               */
+    double t_default;      /* step when the quadratic model is not convex (default 0.3)       */
+    double tau_E_ulps;     /* energy-test slack in ulps of sum |E parts| (default 64)         */
+    double switch_res;     /* mixed precision: FP32 -> FP64 when ||r||_inf <= this (1e-5)     */
+    int32_t check_every;   /* host polls the device state every k iterations (default 16)     */
+    int32_t debug_flags;   /* bit0: force first trial step debug_t; bit1: force c2 = debug_c2 */
+    double debug_t;
+    double debug_c2;
+    int32_t stall_window;  /* mixed: switch to FP64 if ||r||_inf has not improved this long   */
+    int32_t use_graph;     /* 1: replay iterations from a captured HIP graph (default 1)     */
+} bec_pcg_opts;
+
+typedef struct {
+    int32_t status;        /* BEC_OK, BEC_ENOTCONV or BEC_ENUMERIC                             */
+    int32_t iters, halvings, psd_resets, forced_accepts, fp32_iters;
+    double res_inf, step_inf;
+    bec_energies e;
+} bec_pcg_result;
+
+typedef struct bec_grid_s* bec_grid;
+
+const char* bec_status_string(int status);
+const char* bec_last_error(void);
+int bec_version(void);
+
+/* Workspace size in bytes for a grid and precision. */
+int bec_workspace_bytes(const bec_grid_desc* desc, int precision, size_t* bytes);
+
+/* Creates a handle over a caller-owned device workspace (>= bec_workspace_bytes, 256-byte
+ * aligned) on `hip_stream`. Computes nothing yet. */
+int bec_init_grid(const bec_grid_desc* desc, int precision, void* d_workspace, size_t ws_bytes,
+                  void* hip_stream, bec_grid* out);
+int bec_destroy_grid(bec_grid g);
+
+/* Truncated-kernel Fourier integral U_k of U = 1/(4 pi |y|) over the twofold box (Sec. 2.2,
+ * eq. "FUk"; precomputed once per box and grid, Remark after eq. "U_TrunFour"), in FP64 on
+ * every grid. It is real and even in each frequency, independent of the dipole axis; stored
+ * as the octant [Nx+1][Ny+1][Nz+1] (index k_a = 0..N_a of the 2N_a-point padded axis).
+ * Written to the workspace; also copied to d_uhat_octant if it is not NULL. */
+int bec_atkm_symbol(bec_grid g, double* d_uhat_octant);
+
+/* Dipolar potential Phi = U_dip * |phi|^2 on the grid by ATKM (Sec. 2.2, eqs. "DDI2Cou3D",
+ * "fouriercoeff", "U_TrunFour"). Needs bec_atkm_symbol first. */
+int bec_dipolar(bec_grid g, const bec_params* p, const void* d_phi, void* d_Phi);
+
+/* H_phi phi = -1/2[[Lap]]phi + (V + beta|phi|^2 + lambda Phi)phi - Omega [[L_z]]phi
+ * (Sec. 2.3, Euclidean gradient). d_hphi must not alias d_phi. Optional outputs: d_Phi (real
+ * field) and d_mu (one double on the device, mu = <H phi, phi>). */
+int bec_apply_H(bec_grid g, const bec_params* p, const void* d_phi, void* d_hphi,
+                void* d_Phi, double* d_mu);
+
+/* Energy parts of phi (Sec. 2.3 discrete energy; Sec. 3 virial identity). `out` is a host
+ * pointer if out_on_host != 0 (the call then synchronises), else a device pointer. */
+int bec_energy(bec_grid g, const bec_params* p, const void* d_phi, bec_energies* out,
+               int out_on_host);
+
+/* Algorithm 1 (PCG-ATKM) from the guess in d_phi (normalised by the caller, complex128 on
+ * FP64 grids; on FP32 grids complex128 too: the bulk runs in FP32 and a final FP64 phase on
+ * `fp64_grid` polishes to tol_res_inf). Overwrites d_phi with the result. `opts` may be NULL
+ * (defaults). Synchronises. */
+int bec_pcg_solve(bec_grid g, const bec_params* p, void* d_phi, const bec_pcg_opts* opts,
+                  bec_pcg_result* h_result);
+int bec_pcg_default_opts(bec_pcg_opts* opts);
+
+/* 3-D C2C FFT on the N grid (unnormalised; dir = -1 forward exp(-2 pi i jk/N), +1 inverse),
+ * the transform of the Fourier coefficients (eq. "FourphiCo") used by the operators. */
+int bec_fft3d(bec_grid g, const void* d_in, void* d_out, int dir);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEC_H */

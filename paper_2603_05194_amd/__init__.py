@@ -1,0 +1,263 @@
+"""MI355X-native PCG-ATKM ground states of rotating dipolar BECs.
+
+Thin ctypes binding over libbec.so (HIP kernels for gfx950 + C ABI, see include/bec.h).
+The functions named bec_* marshal arguments only; every step of the computation runs in
+the library's kernels. torch provides device memory and the stream.
+
+The library must be built (python -m paper_2603_05194_amd.build); importing the binding
+without it raises at first use, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbec.so")
+
+BEC_OK, BEC_EINVAL, BEC_ENOMEM, BEC_EHIP, BEC_ENOTCONV, BEC_ENUMERIC, BEC_ESTALL = 0, -1, -2, -3, -4, -5, -6
+BEC_FP64, BEC_FP32 = 0, 1
+
+
+class bec_grid_desc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("a", C.c_double * 3)]
+
+
+class bec_params(C.Structure):
+    _fields_ = [("gamma", C.c_double * 3), ("beta", C.c_double), ("lambda_", C.c_double),
+                ("n", C.c_double * 3), ("omega", C.c_double)]
+
+
+class bec_energies(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("E", "Ekin", "Epot", "Eint", "Edip", "Erot", "mu", "mass", "virial")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class bec_pcg_opts(C.Structure):
+    _fields_ = [("tol_res_inf", C.c_double), ("tol_step_inf", C.c_double), ("max_iter", C.c_int32),
+                ("max_halvings", C.c_int32), ("t_default", C.c_double), ("tau_E_ulps", C.c_double),
+                ("switch_res", C.c_double), ("check_every", C.c_int32), ("debug_flags", C.c_int32),
+                ("debug_t", C.c_double), ("debug_c2", C.c_double), ("stall_window", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class bec_pcg_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("halvings", C.c_int32),
+                ("psd_resets", C.c_int32), ("forced_accepts", C.c_int32), ("fp32_iters", C.c_int32),
+                ("res_inf", C.c_double), ("step_inf", C.c_double), ("e", bec_energies)]
+
+
+class BecError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {code} ({_lib().bec_status_string(code).decode()}): "
+                         f"{_lib().bec_last_error().decode()}")
+
+
+_LIB = None
+_SIGS = {
+    "bec_status_string": (C.c_char_p, [C.c_int]),
+    "bec_last_error": (C.c_char_p, []),
+    "bec_version": (C.c_int, []),
+    "bec_workspace_bytes": (C.c_int, [C.POINTER(bec_grid_desc), C.c_int, C.POINTER(C.c_size_t)]),
+    "bec_init_grid": (C.c_int, [C.POINTER(bec_grid_desc), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                                C.POINTER(C.c_void_p)]),
+    "bec_destroy_grid": (C.c_int, [C.c_void_p]),
+    "bec_atkm_symbol": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "bec_dipolar": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_void_p]),
+    "bec_apply_H": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bec_energy": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_void_p, C.c_int]),
+    "bec_pcg_solve": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.POINTER(bec_pcg_opts),
+                                C.POINTER(bec_pcg_result)]),
+    "bec_pcg_default_opts": (C.c_int, [C.POINTER(bec_pcg_opts)]),
+    "bec_fft3d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_05194_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc, where, ok=(BEC_OK,)):
+    if rc not in ok:
+        raise BecError(rc, where)
+    return rc
+
+
+# ------------------------------------------------------------------ raw binding (same names)
+def bec_workspace_bytes(desc: bec_grid_desc, precision: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib().bec_workspace_bytes(C.byref(desc), precision, C.byref(out)), "bec_workspace_bytes")
+    return out.value
+
+
+def bec_init_grid(desc, precision, d_ws, ws_bytes, stream):
+    h = C.c_void_p()
+    _check(_lib().bec_init_grid(C.byref(desc), precision, C.c_void_p(d_ws), ws_bytes, C.c_void_p(stream),
+                                C.byref(h)), "bec_init_grid")
+    return h
+
+
+def bec_destroy_grid(h):
+    return _lib().bec_destroy_grid(h)
+
+
+def bec_atkm_symbol(h, d_out=None):
+    _check(_lib().bec_atkm_symbol(h, C.c_void_p(d_out) if d_out else None), "bec_atkm_symbol")
+
+
+def bec_dipolar(h, params, d_phi, d_Phi):
+    _check(_lib().bec_dipolar(h, C.byref(params), C.c_void_p(d_phi), C.c_void_p(d_Phi)), "bec_dipolar")
+
+
+def bec_apply_H(h, params, d_phi, d_hphi, d_Phi=None, d_mu=None):
+    _check(_lib().bec_apply_H(h, C.byref(params), C.c_void_p(d_phi), C.c_void_p(d_hphi),
+                              C.c_void_p(d_Phi) if d_Phi else None, C.c_void_p(d_mu) if d_mu else None),
+           "bec_apply_H")
+
+
+def bec_energy(h, params, d_phi) -> bec_energies:
+    out = bec_energies()
+    _check(_lib().bec_energy(h, C.byref(params), C.c_void_p(d_phi), C.byref(out), 1), "bec_energy")
+    return out
+
+
+def bec_pcg_default_opts() -> bec_pcg_opts:
+    o = bec_pcg_opts()
+    _check(_lib().bec_pcg_default_opts(C.byref(o)), "bec_pcg_default_opts")
+    return o
+
+
+def bec_pcg_solve(h, params, d_phi, opts=None) -> bec_pcg_result:
+    res = bec_pcg_result()
+    rc = _lib().bec_pcg_solve(h, C.byref(params), C.c_void_p(d_phi), C.byref(opts) if opts is not None else None,
+                              C.byref(res))
+    _check(rc, "bec_pcg_solve", ok=(BEC_OK, BEC_ENOTCONV, BEC_ENUMERIC))
+    return res
+
+
+def bec_fft3d(h, d_in, d_out, direction):
+    _check(_lib().bec_fft3d(h, C.c_void_p(d_in), C.c_void_p(d_out), direction), "bec_fft3d")
+
+
+# ------------------------------------------------------------------ torch-facing helpers
+def make_desc(n, a) -> bec_grid_desc:
+    d = bec_grid_desc()
+    for i in range(3):
+        d.n[i] = int(n[i])
+        d.a[i] = float(a[i])
+    return d
+
+
+def make_params(gamma, beta, lam, ndip, omega) -> bec_params:
+    p = bec_params()
+    for i in range(3):
+        p.gamma[i] = float(gamma[i])
+        p.n[i] = float(ndip[i])
+    p.beta, p.lambda_, p.omega = float(beta), float(lam), float(omega)
+    return p
+
+
+class BecGrid:
+    """Owns a torch-allocated workspace and a library handle for one box/grid."""
+
+    def __init__(self, n, a, precision=BEC_FP64, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.n, self.a = tuple(int(v) for v in n), tuple(float(v) for v in a)
+        self.precision = precision
+        self.desc = make_desc(self.n, self.a)
+        self.ws_bytes = bec_workspace_bytes(self.desc, precision)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        self.handle = bec_init_grid(self.desc, precision, base + off, self.ws_bytes, s.cuda_stream)
+        self._symbol = False
+
+    def close(self):
+        if getattr(self, "handle", None):
+            bec_destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def cdtype(self):
+        return self.torch.complex128 if self.precision == BEC_FP64 else self.torch.complex64
+
+    @property
+    def rdtype(self):
+        return self.torch.float64 if self.precision == BEC_FP64 else self.torch.float32
+
+    def symbol(self):
+        torch = self.torch
+        out = torch.empty((self.n[0] + 1, self.n[1] + 1, self.n[2] + 1), dtype=torch.float64, device=self.device)
+        bec_atkm_symbol(self.handle, out.data_ptr())
+        self._symbol = True
+        return out
+
+    def ensure_symbol(self):
+        if not self._symbol:
+            bec_atkm_symbol(self.handle, None)
+            self._symbol = True
+
+    def _field(self, phi):
+        assert phi.is_contiguous() and phi.dtype == self.cdtype and tuple(phi.shape) == self.n, \
+            f"field must be contiguous {self.cdtype} of shape {self.n}"
+        return phi
+
+    def fft3d(self, u, direction=-1):
+        u = self._field(u)
+        out = self.torch.empty_like(u)
+        bec_fft3d(self.handle, u.data_ptr(), out.data_ptr(), direction)
+        return out
+
+    def dipolar(self, params, phi):
+        self.ensure_symbol()
+        phi = self._field(phi)
+        out = self.torch.empty(self.n, dtype=self.rdtype, device=self.device)
+        bec_dipolar(self.handle, params, phi.data_ptr(), out.data_ptr())
+        return out
+
+    def apply_H(self, params, phi, want_Phi=False):
+        if params.lambda_ != 0.0:
+            self.ensure_symbol()
+        phi = self._field(phi)
+        h = self.torch.empty_like(phi)
+        Phi = self.torch.empty(self.n, dtype=self.rdtype, device=self.device) if want_Phi else None
+        mu = self.torch.empty(1, dtype=self.torch.float64, device=self.device)
+        bec_apply_H(self.handle, params, phi.data_ptr(), h.data_ptr(), Phi.data_ptr() if want_Phi else None,
+                    mu.data_ptr())
+        return (h, mu, Phi) if want_Phi else (h, mu)
+
+    def energy(self, params, phi) -> dict:
+        if params.lambda_ != 0.0:
+            self.ensure_symbol()
+        phi = self._field(phi)
+        return bec_energy(self.handle, params, phi.data_ptr()).as_dict()
+
+    def pcg_solve(self, params, phi, opts=None):
+        if params.lambda_ != 0.0:
+            self.ensure_symbol()
+        assert phi.is_contiguous() and phi.dtype == self.torch.complex128 and tuple(phi.shape) == self.n
+        return bec_pcg_solve(self.handle, params, phi.data_ptr(), opts)

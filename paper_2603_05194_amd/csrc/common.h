@@ -1,0 +1,39 @@
+// Shared device/host definitions: complex type, launch constants, reduction slots.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bec {
+
+template <typename R> struct alignas(2 * sizeof(R)) cpx { R x, y; };
+
+template <typename R> __host__ __device__ __forceinline__ cpx<R> mk(R a, R b) { cpx<R> c; c.x = a; c.y = b; return c; }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return mk(s * a.x, s * a.y); }
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R> __host__ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {  // a * conj(b)
+    return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename R> __host__ __device__ __forceinline__ cpx<R> conj(cpx<R> a) { return mk(a.x, -a.y); }
+// multiply by -i (s = -1) or +i (s = +1)
+template <int S, typename R> __host__ __device__ __forceinline__ cpx<R> mul_i(cpx<R> a) {
+    return S > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+
+constexpr int kThreads = 256;         // threads per block of every field kernel
+constexpr int kTileElems = 4096;      // complex elements held in LDS by one line-FFT block
+constexpr int kMaxStages = 12;
+constexpr int kMaxRed = 32;           // reduction slots per kernel
+
+// Per-size FFT plan (device-visible, passed by value).
+struct FftPlan {
+    int n;
+    int nst;
+    int radix[kMaxStages];
+    const void* tw;                   // n twiddles exp(-2 pi i t / n), element type cpx<R>
+};
+
+}  // namespace bec

@@ -1,0 +1,58 @@
+// Kernel argument structs and host-side launch wrappers (implemented in kernels.hip).
+#pragma once
+#include "common.h"
+
+namespace bec {
+
+// Geometry of one line pass: lines run along `axis` of a C-order 3-D array.
+//  axis 2: a line is `outer` in [0, n_outer) (= i0*d1 + i1), element j at outer*na + j.
+//  axis 0/1: a line is (outer, inner); element j at outer*na*n_inner + j*n_inner + inner.
+//   axis 1: outer = i0, inner = i2; axis 0: outer = 0, inner = i1*d2 + i2.
+struct Geo {
+    int axis;
+    int n_outer, n_inner;
+    int L;            // lines per block
+    int tpo;          // tiles per outer (axes 0/1)
+    int ntiles;
+    int dA, dB;       // axis 2: dA = d1 (to split outer); axis 0: dB = d2 (to split inner)
+};
+
+// Scalars shared between field kernels and the single-thread control kernels (FP64 always).
+struct DevState {
+    // physical parameters and grid constants
+    double gamma[3], beta, lam, nd[3], omega;
+    double h3;
+    // energy parts of the current iterate
+    double Ekin, Epot, Eint, Edip, Erot, E, mu, mass;
+    double res_inf, step_inf, alpha;
+    // preconditioned CG memory and step coefficients
+    double den_prev;
+    double cPr, cPhi, cP;          // p <- cPr * Pr + cPhi * phi + cP * p
+    double cRet, sRet;             // phi <- cRet * phi + sRet * p
+    double t, c2, d1, beta_cg, pnorm;
+    double tau_E;
+    // options
+    double tol_res, tol_step, t_default, tau_ulps;
+    double dbg_t, dbg_c2;
+    int max_iter, max_halv, dbg_flags;
+    // counters and flags
+    int iter, halvings, resets, forced, restart, done, status, accepted_last;
+    int pad_;
+    // reduction landing area (filled by finalize kernels)
+    double red[4][kMaxRed];
+};
+
+enum RedSlot { RS_APPLY = 0, RS_PREC = 1, RS_DIR = 2, RS_AUX = 3 };
+
+template <typename R> struct Tables {
+    FftPlan plan_z, plan_y, plan_x;          // N-grid lengths
+    FftPlan plan_zp, plan_yp, plan_xp;       // padded lengths 2N
+};
+
+struct GridConst {
+    int nx, ny, nz;
+    double ax, ay, az;
+    double hx, hy, hz, h3;
+};
+
+}  // namespace bec

@@ -1,0 +1,100 @@
+"""GPU parity of the operator kernels against the oracle (and numpy's FFT for the transform):
+3-D FFT, truncated-kernel symbol, ATKM dipolar potential, H phi, energy parts."""
+import math
+
+import numpy as np
+import pytest
+
+import bec_inputs as bi
+import paper_2603_05194_amd as bec
+from oracle import symbol as osym, dipolar as odip
+from oracle.energy import Model
+from oracle.grid import Grid
+from tests.gpu_util import dev, host, rel_max, params_of
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 12, 16), (32, 32, 32), (24, 40, 10), (64, 64, 16), (96, 32, 48), (20, 12, 18), (16, 20, 50)]
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_fft3d_matches_numpy(n):
+    g = bec.BecGrid(n, (1.0, 1.0, 1.0))
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    fw = host(g.fft3d(dev(u), -1))
+    assert rel_max(fw, np.fft.fftn(u)) < 1e-14 * max(8, math.log2(np.prod(n)))
+    bw = host(g.fft3d(dev(u), +1))
+    assert rel_max(bw, np.fft.ifftn(u) * np.prod(n)) < 1e-14 * max(8, math.log2(np.prod(n)))
+
+
+@pytest.mark.parametrize("n,a", [((32, 32, 32), (8.0, 8.0, 4.0)), ((12, 20, 8), (3.0, 5.0, 2.0)),
+                                 ((16, 16, 64), (4.0, 4.0, 24.0))])
+def test_symbol_matches_oracle(n, a):
+    g = bec.BecGrid(n, a)
+    got = host(g.symbol())
+    ref = osym.octant(osym.symbol_full(Grid(n, a)), Grid(n, a))
+    assert got.shape == ref.shape
+    # both sides sum the same O(U_0)-sized quadrature terms: the error is absolute, at the
+    # rounding level of U_0, also where U_k itself is small
+    assert rel_max(got, ref) < 1e-13
+
+
+CASES = [
+    ("small_32", None),
+    ("small_32", (20, 12, 18)),
+    ("pancake_256", (32, 32, 8)),
+    ("cigar_128", (16, 16, 32)),
+]
+
+
+def _case(name, n):
+    w = bi.WORKLOADS[name]
+    n = tuple(n or w.n)
+    m = Model.from_workload(w, n=n)
+    phi = bi.initial_guess(w, n)
+    return w, n, m, phi
+
+
+@pytest.mark.parametrize("name,n", CASES)
+def test_dipolar_matches_oracle(name, n):
+    w, n, m, phi = _case(name, n)
+    g = bec.BecGrid(n, w.a)
+    got = host(g.dipolar(params_of(m), dev(phi)))
+    ref = m.Phi(np.abs(phi) ** 2)
+    assert rel_max(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("name,n", CASES)
+def test_apply_H_matches_oracle(name, n):
+    w, n, m, phi = _case(name, n)
+    g = bec.BecGrid(n, w.a)
+    h, mu, Phi = g.apply_H(params_of(m), dev(phi), want_Phi=True)
+    ref = m.H(phi)
+    assert rel_max(host(h), ref) < 1e-12
+    e = m.energies(phi)
+    assert abs(float(host(mu)[0]) - e.mu) < 1e-12 * abs(e.mu)
+    assert rel_max(host(Phi), m.Phi(np.abs(phi) ** 2)) < 1e-12
+
+
+@pytest.mark.parametrize("name,n", CASES)
+def test_energy_matches_oracle(name, n):
+    w, n, m, phi = _case(name, n)
+    g = bec.BecGrid(n, w.a)
+    got = g.energy(params_of(m), dev(phi))
+    ref = m.energies(phi).as_dict()
+    scale = sum(abs(ref[k]) for k in ("Ekin", "Epot", "Eint", "Edip", "Erot"))
+    for k in ("E", "Ekin", "Epot", "Eint", "Edip", "Erot", "mu", "mass", "virial"):
+        assert abs(got[k] - ref[k]) < 1e-12 * scale, (k, got[k], ref[k])
+
+
+def test_apply_H_random_field_all_terms():
+    """A rough random field (all Fourier modes populated, Nyquist included)."""
+    n, a = (16, 12, 20), (3.0, 2.0, 2.5)
+    m = Model(n, a, (1.0, 1.7, 2.3), 37.0, -21.0, (0.3, -0.4, math.sqrt(1 - 0.25)), 0.7)
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    phi = bi.normalize(phi, n, a)
+    g = bec.BecGrid(n, a)
+    h, mu = g.apply_H(params_of(m), dev(phi))
+    assert rel_max(host(h), m.H(phi)) < 1e-12
