@@ -1,0 +1,200 @@
+"""North-star benchmark: time to ground state of the 256x256x64 pancake workload (FP64 PCG-ATKM
+on one MI355X), with H phi throughput, PCG iteration rate, the dominant kernel's HBM roofline
+fraction, the mixed-precision path and the CPU oracle baseline on the host cores.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+A step is one full solve (||H phi - mu phi||_inf <= 1e-8) from a seeded random-phase guess;
+inputs are resident in HBM before the timed region. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "s to ground state (res≤1e-8) at 256²×64; H·φ/s; mixed+learned vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def atkm_x_bytes(n, csize):
+    """Algorithmic bytes of one ATKM x pass: read + write the [Nx][2Ny][Nz+1] half spectrum
+    (complex, csize bytes) and read the FP64 symbol octant once."""
+    nx, ny, nz = n
+    return 2 * nx * 2 * ny * (nz + 1) * csize + (nx + 1) * (ny + 1) * (nz + 1) * 8
+
+
+def cpu_baseline(w, gpu_iters, n_iter=2):
+    import numpy as np
+    import bec_inputs as bi
+    from oracle import spectral
+    from oracle.energy import Model
+    from oracle.pcg import pcg
+    from oracle import symbol
+    cores = spectral.WORKERS
+    t0 = time.perf_counter()
+    uh = symbol.symbol_full_by_octant(__import__("oracle.grid", fromlist=["Grid"]).Grid(w.n, w.a))
+    t_sym = time.perf_counter() - t0
+    m = Model.from_workload(w, uhat_full=uh)
+    phi0 = bi.initial_guess(w)
+    t0 = time.perf_counter()
+    m.energies(phi0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pcg(m, phi0, max_iter=n_iter)
+    t_it = (time.perf_counter() - t0 - t_setup) / n_iter
+    cpu = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": t_it * gpu_iters, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_iter} oracle PCG iterations (FP64 NumPy/SciPy FFT) of the same 256x256x64 workload; "
+                      f"{t_it:.2f} s/iteration x {gpu_iters} GPU FP64 iterations = extrapolated time to ground "
+                      f"state; symbol precompute {t_sym:.1f} s excluded",
+            "s_per_iter": t_it, "cpu_model": cpu, "numpy": np.__version__}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="reduced grid (for testing the script)")
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="cap PCG iterations (profiling runs only; the result is then not a ground state)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import bec_inputs as bi
+    import paper_2603_05194_amd as bec
+
+    w = bi.WORKLOADS["pancake_256"]
+    if args.quick:
+        w = w.with_grid((64, 64, 16))
+    n = w.n
+    p = bec.make_params(w.gamma, w.beta, w.lam, w.ndip, w.omega)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    g = bec.BecGrid(n, w.a)
+    g.ensure_symbol()
+    torch.cuda.synchronize()
+    t_symbol = time.perf_counter() - t0
+    log(f"grid {n} symbol+init {t_symbol:.3f}s")
+
+    def guess(seed):
+        ws = bi.Workload(**{**w.to_dict(), "seed": seed})
+        return torch.from_numpy(bi.initial_guess(ws)).to(dev)
+
+    warm = [guess(1000 + i) for i in range(args.warmup)]
+    steps = [guess(i) for i in range(args.steps)]
+    opts = bec.bec_pcg_default_opts()
+    if args.max_iter is not None:
+        opts.max_iter = args.max_iter
+    for i, phi in enumerate(warm):
+        r = g.pcg_solve(p, phi, opts)
+        log(f"warmup {i}: status {r.status} iters {r.iters} res {r.res_inf:.2e} E {r.e.E:.12f}")
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for i, phi in enumerate(steps):
+        results.append(g.pcg_solve(p, phi, opts))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    for i, r in enumerate(results):
+        log(f"step {i}: status {r.status} iters {r.iters} res {r.res_inf:.2e} E {r.e.E:.12f} mu {r.e.mu:.12f}")
+    iters = [r.iters for r in results]
+    s_per_solve = t_total / args.steps
+    it_per_s = sum(iters) / t_total
+
+    # H phi applies/s and the dominant kernel, timed with HIP events on the library stream
+    phi = steps[0]
+    t_apply_ms = g.time_stage(p, phi, 2, reps=20)
+    t_atkm_ms = g.time_stage(p, phi, 1, reps=20)
+    t_x_ms = g.time_stage(p, phi, 0, reps=50)
+    x_bytes = atkm_x_bytes(n, 16)
+    achieved = x_bytes / (t_x_ms * 1e-3) / 1e9
+    log(f"apply {t_apply_ms:.3f} ms, atkm {t_atkm_ms:.3f} ms, atkm x pass {t_x_ms:.3f} ms -> {achieved:.0f} GB/s")
+
+    mixed = None
+    if not args.no_mixed:
+        gm = bec.BecGrid(n, w.a, precision=bec.BEC_FP32)
+        gm.ensure_symbol()
+        phim = guess(0)
+        rm = gm.pcg_solve(p, phim, opts)     # warm
+        phim = guess(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rm = gm.pcg_solve(p, phim, opts)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        ref = results[0]
+        mixed = {"s_to_ground_state": tm, "iters": rm.iters, "fp32_iters": rm.fp32_iters, "status": rm.status,
+                 "speedup_vs_fp64": (t_total / args.steps) / tm if args.steps else None,
+                 "dE_vs_fp64": rm.e.E - ref.e.E, "dmu_vs_fp64": rm.e.mu - ref.e.mu}
+        log(f"mixed: {tm:.3f}s iters {rm.iters} (fp32 {rm.fp32_iters}) dE {rm.e.E - ref.e.E:.2e}")
+        del gm
+
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_baseline(w, int(np.median(iters)))
+            log(f"cpu baseline {cpu['s_per_iter']:.2f} s/iter on {cpu['cores']} threads")
+        except Exception as e:   # the baseline never hides the GPU result
+            cpu = {"error": repr(e)}
+
+    out = {
+        "metric": METRIC,
+        "value": s_per_solve,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * s_per_solve,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"pancake trap {n[0]}x{n[1]}x{n[2]} on [-16,16]^2x[-2,2], gamma=(1,1,20), "
+                               f"beta=2000, lambda=600, n=(sin30,0,cos30), Omega=0.9; random-phase Gaussian "
+                               f"guess seeds 0..{args.steps - 1}; FP64 PCG-ATKM to ||r||_inf<=1e-8",
+                   "grid": list(n), "padded": [2 * v for v in n]},
+        "iters_per_solve": iters,
+        "pcg_iters_per_s": it_per_s,
+        "hphi_per_s": 1e3 / t_apply_ms,
+        "atkm_per_s": 1e3 / t_atkm_ms,
+        "symbol_precompute_s": t_symbol,
+        "mixed": mixed,
+        "learned": None,
+        "roofline": {"bound": "hbm", "kernel": "k_atkm_x (padded x pass: forward, S' multiply, inverse)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": x_bytes, "avg_ms": t_x_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

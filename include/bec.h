@@ -16,8 +16,9 @@
  *  - Inner product <u, v> = Re(h_x h_y h_z sum u conj(v)) (eq. "innerPro"); ||.||_inf unweighted.
  *  - Ownership: the caller owns every device buffer and the workspace (it asks
  *    bec_workspace_bytes for the size and allocates it). The handle holds host metadata and
- *    views into the workspace; the library never allocates or frees device memory except in
- *    bec_init_grid for a few KB of twiddle/quadrature tables, released by bec_destroy_grid.
+ *    views into the workspace (twiddle and quadrature tables included); the library never
+ *    allocates device memory. bec_pcg_solve creates and destroys a private stream, an event
+ *    and a HIP graph per call.
  *  - Streams: all work is enqueued on the stream given to bec_init_grid (a hipStream_t, or
  *    NULL for the default stream) and is asynchronous, except calls that return host data
  *    (bec_energy with out_on_host, bec_pcg_solve), which synchronise that stream.
@@ -122,10 +123,13 @@ int bec_apply_H(bec_grid g, const bec_params* p, const void* d_phi, void* d_hphi
 int bec_energy(bec_grid g, const bec_params* p, const void* d_phi, bec_energies* out,
                int out_on_host);
 
-/* Algorithm 1 (PCG-ATKM) from the guess in d_phi (normalised by the caller, complex128 on
- * FP64 grids; on FP32 grids complex128 too: the bulk runs in FP32 and a final FP64 phase on
- * `fp64_grid` polishes to tol_res_inf). Overwrites d_phi with the result. `opts` may be NULL
- * (defaults). Synchronises. */
+/* Algorithm 1 (PCG-ATKM) from the guess in d_phi (complex128, normalised by the caller) to
+ * ||H phi - mu phi||_inf <= tol_res_inf. On BEC_FP64 grids every field is FP64. On BEC_FP32
+ * grids the bulk runs on FP32 fields (FP64 reductions, energies and step coefficients) until
+ * ||r||_inf <= switch_res or the residual stalls, then the same grid's FP64 buffers polish
+ * from the renormalised FP32 result with a CG restart. Overwrites d_phi with the result.
+ * `opts` may be NULL (defaults). Returns BEC_OK, BEC_ENOTCONV or BEC_ENUMERIC (the result
+ * struct is filled in all three cases). Synchronises. */
 int bec_pcg_solve(bec_grid g, const bec_params* p, void* d_phi, const bec_pcg_opts* opts,
                   bec_pcg_result* h_result);
 int bec_pcg_default_opts(bec_pcg_opts* opts);
@@ -133,6 +137,13 @@ int bec_pcg_default_opts(bec_pcg_opts* opts);
 /* 3-D C2C FFT on the N grid (unnormalised; dir = -1 forward exp(-2 pi i jk/N), +1 inverse),
  * the transform of the Fourier coefficients (eq. "FourphiCo") used by the operators. */
 int bec_fft3d(bec_grid g, const void* d_in, void* d_out, int dir);
+
+/* Measurement helper: runs one stage of the hot path `reps` times on the grid's stream and
+ * returns the mean duration per run from HIP events (milliseconds). which = 0: the ATKM
+ * padded x pass (forward, symbol multiply, inverse) on the current ATKM buffer; 1: the whole
+ * ATKM potential of |phi|^2; 2: the whole H phi apply; 3: the 3-D FFT of phi (forward).
+ * Needs bec_atkm_symbol for which = 0..2. Synchronises. */
+int bec_time_stage(bec_grid g, const bec_params* p, const void* d_phi, int which, int reps, double* avg_ms);
 
 #ifdef __cplusplus
 }

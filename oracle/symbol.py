@@ -95,6 +95,23 @@ def symbol_full(grid, chunk=4):
     return out
 
 
+def symbol_full_by_octant(grid, chunk=4):
+    """U_k on the whole padded grid from its values at k_a = 0..N_a: I(s; nu, b) is even in nu
+    (cos is even), so U_k depends on |k_a| only. Same sums as symbol_full, 8x fewer of them."""
+    pg = grid.padded()
+    tau, w = tau_nodes()
+    coef = w * np.exp(tau) / (2.0 * math.pi ** 1.5)
+    T = [axis_tables(pg.n[d], pg.a[d])[:, : grid.n[d] + 1] for d in range(3)]
+    nx, ny, nz = (v + 1 for v in grid.n)
+    oct_ = np.empty((nx, ny, nz))
+    Tyz = T[1][:, :, None] * T[2][:, None, :]
+    for i0 in range(0, nx, chunk):
+        blk = (coef[:, None] * T[0][:, i0:i0 + chunk])[:, :, None, None] * Tyz[:, None, :, :]
+        oct_[i0:i0 + chunk] = np.sum(blk, axis=0)
+    idx = [np.abs(np.fft.fftfreq(pg.n[d], 1.0 / pg.n[d])).astype(int) for d in range(3)]
+    return oct_[np.ix_(idx[0], idx[1], idx[2])]
+
+
 def symbol_at(grid, kx, ky, kz):
     """U_k for given padded-grid FFT-order indices (arrays of equal length)."""
     pg = grid.padded()

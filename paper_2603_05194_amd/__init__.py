@@ -73,6 +73,8 @@ _SIGS = {
                                 C.POINTER(bec_pcg_result)]),
     "bec_pcg_default_opts": (C.c_int, [C.POINTER(bec_pcg_opts)]),
     "bec_fft3d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "bec_time_stage": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.c_int,
+                                 C.POINTER(C.c_double)]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -151,6 +153,12 @@ def bec_pcg_solve(h, params, d_phi, opts=None) -> bec_pcg_result:
 
 def bec_fft3d(h, d_in, d_out, direction):
     _check(_lib().bec_fft3d(h, C.c_void_p(d_in), C.c_void_p(d_out), direction), "bec_fft3d")
+
+
+def bec_time_stage(h, params, d_phi, which, reps) -> float:
+    ms = C.c_double(0.0)
+    _check(_lib().bec_time_stage(h, C.byref(params), C.c_void_p(d_phi), which, reps, C.byref(ms)), "bec_time_stage")
+    return ms.value
 
 
 # ------------------------------------------------------------------ torch-facing helpers
@@ -255,6 +263,10 @@ class BecGrid:
             self.ensure_symbol()
         phi = self._field(phi)
         return bec_energy(self.handle, params, phi.data_ptr()).as_dict()
+
+    def time_stage(self, params, phi, which, reps=10):
+        self.ensure_symbol()
+        return bec_time_stage(self.handle, params, self._field(phi).data_ptr(), which, reps)
 
     def pcg_solve(self, params, phi, opts=None):
         if params.lambda_ != 0.0:

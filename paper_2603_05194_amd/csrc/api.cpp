@@ -1,6 +1,8 @@
 // C ABI of the PCG-ATKM library: validation, workspace carving, FFT plans, entry points.
 #include <hip/hip_runtime.h>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -215,6 +217,149 @@ int check_launch(Grid* g, const char* where) {
     return BEC_OK;
 }
 
+// ------------------------------------------------------------------ PCG driver
+// Runs Algorithm 1 with all scalar decisions on the device. The host enqueues iterations
+// (eagerly for the first two, then as a captured two-iteration HIP graph) on a private
+// non-blocking stream and reads the device state every check_every iterations.
+struct HostPoll { int done, status, iter; double res; };
+
+int read_state(Grid& g, DevState& hs) {
+    hipError_t e = hipMemcpyAsync(&hs, g.st, sizeof(DevState), hipMemcpyDeviceToHost, g.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+    if (e != hipSuccess) return hip_fail(&g, e, "state readback");
+    return BEC_OK;
+}
+
+template <typename R>
+int pcg_phase(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi, const bec_pcg_opts& o, bool stall_stop,
+              DevState& hs) {
+    int rc;
+    launch_pcg_start<R>(g, f, p, phi);
+    if ((rc = check_launch(&g, "pcg start"))) return rc;
+    const int every = o.check_every;
+    long it = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double best = 1e300;
+    long best_it = 0;
+    int polls_since = 0;
+    const char* prog = std::getenv("BEC_PROGRESS");
+    const double prog_every = prog ? std::atof(prog) : 0.0;
+    double last_print = 0.0;
+    auto now = []() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
+    if (prog_every > 0) last_print = now();
+    for (;;) {
+        if (o.use_graph && it >= 2 && (it & 1) == 0) {
+            if (!exec) {
+                hipError_t e = hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return hip_fail(&g, e, "begin capture");
+                launch_pcg_iteration<R>(g, f, p, phi, 0);
+                launch_pcg_iteration<R>(g, f, p, phi, 1);
+                e = hipStreamEndCapture(g.stream, &graph);
+                if (e != hipSuccess) return hip_fail(&g, e, "end capture");
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) return hip_fail(&g, e, "graph instantiate");
+            }
+            hipError_t e = hipGraphLaunch(exec, g.stream);
+            if (e != hipSuccess) return hip_fail(&g, e, "graph launch");
+            it += 2;
+        } else {
+            launch_pcg_iteration<R>(g, f, p, phi, (int)(it & 1));
+            it += 1;
+        }
+        if ((rc = check_launch(&g, "pcg iteration"))) break;
+        if (it % every == 0 || it < 2) {
+            if ((rc = read_state(g, hs))) break;
+            if (prog_every > 0 && now() - last_print >= prog_every) {
+                std::fprintf(stderr, "[bec] %s iter %d res %.3e E %.15f\n", sizeof(R) == 4 ? "fp32" : "fp64", hs.iter,
+                             hs.res_inf, hs.E);
+                std::fflush(stderr);
+                last_print = now();
+            }
+            if (hs.done) break;
+            if (stall_stop) {
+                if (hs.res_inf < 0.999 * best) { best = hs.res_inf; best_it = hs.iter; polls_since = 0; }
+                else if (hs.iter - best_it >= o.stall_window) break;
+                (void)polls_since;
+            }
+        }
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (rc) return rc;
+    return read_state(g, hs);
+}
+
+int pcg_solve(Grid& g, const Params& p, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* res) {
+    hipStream_t user = g.stream;
+    hipStream_t ps = nullptr;
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ps, ev, 0);
+    if (e != hipSuccess) return hip_fail(&g, e, "solve stream");
+    g.stream = ps;
+    const long N = (long)g.n[0] * g.n[1] * g.n[2];
+    CtlOpts co;
+    co.tol_res = o.tol_res_inf; co.tol_step = o.tol_step_inf; co.t_default = o.t_default; co.tau_ulps = o.tau_E_ulps;
+    co.dbg_t = o.debug_t; co.dbg_c2 = o.debug_c2; co.max_iter = o.max_iter; co.max_halv = o.max_halvings;
+    co.dbg_flags = o.debug_flags; co.fp32 = g.precision;
+    DevState hs;
+    std::memset(&hs, 0, sizeof(hs));
+    int rc = BEC_OK;
+    int fp32_iters = 0;
+    // clear reductions and the CG memory buffers once (outside any captured graph)
+    e = hipMemsetAsync(g.st->red, 0, sizeof(g.st->red), g.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.f64.p, 0, N * sizeof(cpx<double>), g.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.f64.r1, 0, N * sizeof(cpx<double>), g.stream);
+    if (e != hipSuccess) rc = hip_fail(&g, e, "solve init");
+    if (!rc && g.precision == BEC_FP32) {
+        // FP32 bulk phase: stop at ||r||_inf <= switch_res or when the residual stalls
+        co.tol_res = std::max(o.switch_res, o.tol_res_inf);
+        launch_ctl_init(g, co);
+        e = hipMemsetAsync(g.f32.p, 0, N * sizeof(cpx<float>), g.stream);
+        if (e == hipSuccess) e = hipMemsetAsync(g.f32.r1, 0, N * sizeof(cpx<float>), g.stream);
+        if (e != hipSuccess) rc = hip_fail(&g, e, "solve init");
+        if (!rc) {
+            launch_to_f32(g, phi, g.f32.phi);
+            rc = pcg_phase<float>(g, g.f32, p, g.f32.phi, o, true, hs);
+        }
+        if (!rc) {
+            fp32_iters = hs.iter;
+            if (hs.status == BEC_ENUMERIC) {
+                // keep the caller's guess untouched; fall through to the FP64 phase from it
+            } else {
+                launch_to_f64_normalized(g, g.f32.phi, phi);
+            }
+            launch_ctl_phase(g, o.tol_res_inf, o.max_iter);
+            rc = check_launch(&g, "phase switch");
+        }
+        if (!rc) rc = pcg_phase<double>(g, g.f64, p, phi, o, false, hs);
+    } else if (!rc) {
+        launch_ctl_init(g, co);
+        rc = pcg_phase<double>(g, g.f64, p, phi, o, false, hs);
+    }
+    hipStreamSynchronize(ps);
+    g.stream = user;
+    hipEventDestroy(ev);
+    hipStreamDestroy(ps);
+    if (rc) return rc;
+    res->status = hs.status == 0 ? BEC_OK : hs.status;
+    res->iters = hs.iter;
+    res->halvings = hs.halvings;
+    res->psd_resets = hs.resets;
+    res->forced_accepts = hs.forced;
+    res->fp32_iters = fp32_iters;
+    res->res_inf = hs.res_inf;
+    res->step_inf = hs.step_inf;
+    res->e.E = hs.E; res->e.Ekin = hs.Ekin; res->e.Epot = hs.Epot; res->e.Eint = hs.Eint;
+    res->e.Edip = hs.Edip; res->e.Erot = hs.Erot; res->e.mu = hs.mu; res->e.mass = hs.mass;
+    res->e.virial = 2 * hs.Ekin - 2 * hs.Epot + 3 * hs.Eint + 3 * hs.Edip;
+    if (res->status != BEC_OK) g_last_error = bec_status_string(res->status);
+    return res->status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -286,6 +431,7 @@ int bec_init_grid(const bec_grid_desc* desc, int precision, void* d_ws, size_t w
     g->g_ax = make_geo(0, nx, 2 * ny, nz + 1, 2 * nx, 0);
     g->g_ax2 = make_geo(0, nx, 2 * ny, nz + 1, 2 * nx, 1);
     g->zf_L = std::max(1, kTileElems / (2 * nz));
+    if (const char* e = std::getenv("BEC_GENERIC_FFT")) g->use_rf = std::atoi(e) ? 0 : 1;
     g->zf2_L = g->zf_L;
     g->zi_L = g->zf_L;
     if ((rc = make_plans<double>(*g, g->f64, g->ws + L.tw64))) { delete g; return rc; }
@@ -415,8 +561,32 @@ int bec_pcg_default_opts(bec_pcg_opts* o) {
 }
 
 int bec_pcg_solve(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_opts* opts, bec_pcg_result* res) {
-    (void)g; (void)pp; (void)d_phi; (void)opts; (void)res;
-    return fail(BEC_EINVAL, "not implemented yet");
+    int rc = check_grid(g);
+    if (rc) return rc;
+    Params p;
+    if ((rc = validate_params(pp, p))) return rc;
+    if (!d_phi || !res) return fail(BEC_EINVAL, "NULL pointer");
+    bec_pcg_opts o;
+    if (opts) o = *opts; else bec_pcg_default_opts(&o);
+    if (!(o.tol_res_inf >= 0.0) || o.max_iter < 0 || o.max_halvings < 0 || o.check_every < 1)
+        return fail(BEC_EINVAL, "bad options");
+    if (p.lam != 0.0 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    return pcg_solve(*g, p, (cpx<double>*)d_phi, o, res);
+}
+
+int bec_time_stage(bec_grid g, const bec_params* pp, const void* d_phi, int which, int reps, double* avg_ms) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    Params p;
+    if ((rc = validate_params(pp, p))) return rc;
+    if (!d_phi || !avg_ms || reps < 1 || which < 0 || which > 3) return fail(BEC_EINVAL, "bad arguments");
+    if (which <= 2 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    launch_set_params(*g, p);
+    if (g->precision == BEC_FP64)
+        *avg_ms = time_stage<double>(*g, g->f64, p, (const cpx<double>*)d_phi, which, reps);
+    else
+        *avg_ms = time_stage<float>(*g, g->f32, p, (const cpx<float>*)d_phi, which, reps);
+    return check_launch(g, "time_stage");
 }
 
 }  // extern "C"

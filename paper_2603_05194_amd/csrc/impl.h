@@ -50,6 +50,7 @@ struct Grid {
     double* sym_scratch = nullptr;
     size_t sym_scratch_bytes = 0;
     int poisoned = 0;
+    int use_rf = 1;           // power-of-two register-FFT fast paths (0: generic LDS kernels)
     // geometries
     Geo gz, gy, gx;           // N grid line passes (z: Nz, y: Ny, x: Nx)
     Geo g_ay, g_ax, g_ax2, g_ayi;   // padded passes
@@ -70,8 +71,16 @@ template <typename R> void launch_apply(Grid& g, Fields<R>& f, const Params& p, 
 void launch_symbol(Grid& g, std::vector<double>& tables_host_scratch);
 void launch_set_params(Grid& g, const Params& p);
 
+struct CtlOpts {
+    double tol_res, tol_step, t_default, tau_ulps, dbg_t, dbg_c2;
+    int max_iter, max_halv, dbg_flags, fp32;
+};
 template <typename R> void launch_pcg_iteration(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi, int parity);
 template <typename R> void launch_pcg_start(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi);
-void launch_control_init(Grid& g, const double* opts_d, int nopts);
+void launch_ctl_init(Grid& g, const CtlOpts& o);
+void launch_ctl_phase(Grid& g, double tol, int max_iter);
+template <typename R> double time_stage(Grid& g, Fields<R>& f, const Params& p, const cpx<R>* phi, int which, int reps);
+void launch_to_f32(Grid& g, const cpx<double>* a, cpx<float>* b);
+void launch_to_f64_normalized(Grid& g, const cpx<float>* a, cpx<double>* b);
 
 }  // namespace bec

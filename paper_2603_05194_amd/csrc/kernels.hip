@@ -9,6 +9,8 @@
 //   preconditioner: 3-D FFT with P_V^{1/2} scaling on the z passes, shift division on x
 // Reductions are FP64 per block (wave shuffles + LDS), finished by a fixed-order tree.
 #include "lines.h"
+#include "impl.h"
+#include "regfft.h"
 
 namespace bec {
 
@@ -512,6 +514,9 @@ template <typename R>
 __global__ void k_copy_state_scalar(const DevState* st, int which, double* out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = which == 0 ? st->mu : st->E;
 }
+
+#include "pcg.inc"
+#include "rfkern.inc"
 
 }  // namespace bec
 

@@ -1,0 +1,120 @@
+// Register-resident batched FFT for power-of-two line lengths known at compile time.
+//
+// A block of 256 threads transforms L lines of N points; each thread keeps E points of one
+// line in registers. Stage s of radix R_s (radix 2 or 4 first when log2 N is not a multiple of
+// 3, then radix 8) applies the Stockham step
+//   v_k = x[j + k N/R] * w^(k (j mod Ns)),  v = DFT_R(v),  y[(j - j mod Ns) R + j mod Ns + k Ns] = v_k
+// to the E/R butterflies j = jb + (N/E) b of the thread; between stages the points go through
+// LDS once (write outputs, barrier, read the next stage's inputs, barrier).
+//
+// Register layouts: on entry v[b R_first + k] = x[jb + (N/E) b + k N/R_first]; on exit
+// v[b R_last + k] = X[jb + (N/E) b + k N/R_last] (natural-order frequency index). The inverse
+// transform runs the stages in reverse order, so an inverse started from a forward's exit
+// layout ends in the forward's entry layout: forward -> pointwise multiply -> inverse needs no
+// extra data movement.
+#pragma once
+#include "common.h"
+#include "fft.h"
+
+namespace bec {
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+template <int N> struct Pow2Plan {
+    static constexpr int p = ilog2(N);
+    static constexpr int rem = p % 3;
+    static constexpr int ns = p / 3 + (rem ? 1 : 0);
+    // forward order: the small radix first
+    static constexpr int fwd(int s) { return (rem && s == 0) ? (1 << rem) : 8; }
+    static constexpr int inv(int s) { return fwd(ns - 1 - s); }
+    template <int DIR> static constexpr int radix(int s) { return DIR < 0 ? fwd(s) : inv(s); }
+    template <int DIR> static constexpr int span(int s) {   // product of the radices before s
+        return s == 0 ? 1 : span<DIR>(s - 1) * radix<DIR>(s - 1);
+    }
+};
+
+// points per thread: enough lines per block for 128-byte column segments, at least 8
+template <typename R> constexpr int rf_points(int N) {
+    const int per_seg = 128 / (int)sizeof(cpx<R>);          // complex values per 128 B
+    int e = per_seg * N / kThreads;
+    if (e < 8) e = 8;
+    if (e > 32) e = 32;
+    if (e > N) e = N;
+    return e;
+}
+
+template <typename R, int N, int E> struct RF {
+    static constexpr int TPL = N / E;          // threads per line
+    static constexpr int L = kThreads / TPL;   // lines per block
+    static constexpr int LD = N + 1;           // LDS line stride (odd: spreads banks)
+    static constexpr size_t lds_bytes = (size_t)L * LD * sizeof(cpx<R>);
+};
+
+template <typename R, int N, int E, int DIR, int S>
+__device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line, int jb,
+                                       const cpx<R>* __restrict__ tw) {
+    using P = Pow2Plan<N>;
+    constexpr int RD = P::template radix<DIR>(S);
+    constexpr int Ns = P::template span<DIR>(S);
+    constexpr int TPL = N / E;
+    constexpr int BPT = E / RD;
+    static_assert(E % RD == 0, "points per thread must be a multiple of every radix");
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int j = jb + TPL * b;
+        if constexpr (Ns > 1) {
+            const int jm = j & (Ns - 1);
+#pragma unroll
+            for (int k = 1; k < RD; ++k) {
+                cpx<R> w = tw[jm * k * (N / (Ns * RD))];
+                if constexpr (DIR > 0) w = conj(w);
+                v[b * RD + k] = cmul(v[b * RD + k], w);
+            }
+        }
+        dft_small<RD, DIR>(&v[b * RD]);
+    }
+    if constexpr (S + 1 < P::ns) {
+        constexpr int RN = P::template radix<DIR>(S + 1);
+        constexpr int BN = E / RN;
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int j = jb + TPL * b;
+            const int jm = j & (Ns - 1);
+            cpx<R>* o = line + (j - jm) * RD + jm;
+#pragma unroll
+            for (int k = 0; k < RD; ++k) o[k * Ns] = v[b * RD + k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < BN; ++b) {
+            const int j = jb + TPL * b;
+#pragma unroll
+            for (int k = 0; k < RN; ++k) v[b * RN + k] = line[j + k * (N / RN)];
+        }
+        __syncthreads();
+        rf_run<R, N, E, DIR, S + 1>(v, line, jb, tw);
+    }
+}
+
+// Full transform; `line` is this thread's line in LDS (lds + l * LD).
+template <typename R, int N, int E, int DIR>
+__device__ __forceinline__ void rf_fft(cpx<R> (&v)[E], cpx<R>* line, int jb, const cpx<R>* tw) {
+    rf_run<R, N, E, DIR, 0>(v, line, jb, tw);
+}
+
+// Index (within the line) of register slot i for the entry layout of direction DIR
+// (i.e. the layout rf_fft<DIR> expects on entry).
+template <int N, int E, int DIR> __device__ __forceinline__ int rf_in_index(int jb, int i) {
+    using P = Pow2Plan<N>;
+    constexpr int RD = P::template radix<DIR>(0);
+    return jb + (N / E) * (i / RD) + (i % RD) * (N / RD);
+}
+
+// Index of register slot i for the exit layout of direction DIR.
+template <int N, int E, int DIR> __device__ __forceinline__ int rf_out_index(int jb, int i) {
+    using P = Pow2Plan<N>;
+    constexpr int RD = P::template radix<DIR>(P::ns - 1);
+    return jb + (N / E) * (i / RD) + (i % RD) * (N / RD);
+}
+
+}  // namespace bec

@@ -98,3 +98,19 @@ def test_apply_H_random_field_all_terms():
     g = bec.BecGrid(n, a)
     h, mu = g.apply_H(params_of(m), dev(phi))
     assert rel_max(host(h), m.H(phi)) < 1e-12
+
+
+@pytest.mark.parametrize("name,n", [("small_32", None), ("pancake_256", (64, 64, 16))])
+def test_generic_and_power_of_two_paths_agree(name, n, monkeypatch):
+    """The compile-time power-of-two FFT kernels and the generic mixed-radix kernels give the
+    same H phi and energies (both within the oracle tolerance)."""
+    w, n, m, phi = _case(name, n)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BEC_GENERIC_FFT", flag)
+        g = bec.BecGrid(n, w.a)
+        h, mu = g.apply_H(params_of(m), dev(phi))
+        out.append((host(h), g.energy(params_of(m), dev(phi))))
+    assert rel_max(out[0][0], out[1][0]) < 1e-13
+    for k in ("E", "mu", "Edip"):
+        assert abs(out[0][1][k] - out[1][1][k]) < 1e-13 * abs(out[1][1][k]) + 1e-15

@@ -352,3 +352,8 @@ def test_pcg_forced_branches():
     assert r.forced > 0
     r = pcg(m, phi0, max_iter=5, debug={"nan_at": 1})
     assert r.status == "numeric"
+
+
+def test_symbol_by_octant_equals_full():
+    g = Grid((8, 6, 10), (3.0, 2.0, 1.5))
+    np.testing.assert_array_equal(symbol.symbol_full_by_octant(g), symbol.symbol_full(g))
