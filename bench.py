@@ -27,11 +27,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def atkm_x_bytes(n, csize):
-    """Algorithmic bytes of one ATKM x pass: read + write the [Nx][2Ny][Nz+1] half spectrum
-    (complex, csize bytes) and read the FP64 symbol octant once."""
+def pass_bytes(which, n, csize):
+    """Algorithmic HBM bytes of one launch of a padded ATKM pass (complex values of csize bytes):
+    y forward: read the [Nx][Ny][Nz+1] z half spectrum, write the [Nx][2Ny][Nz+1] buffer;
+    x pass (forward, S' multiply, inverse): read + write the [Nx][2Ny][Nz+1] buffer and read the
+    FP64 symbol octant [Nx+1][Ny+1][Nz+1] once; dual x Parseval: read two such buffers + octant."""
     nx, ny, nz = n
-    return 2 * nx * 2 * ny * (nz + 1) * csize + (nx + 1) * (ny + 1) * (nz + 1) * 8
+    zh = nx * ny * (nz + 1) * csize
+    yb = nx * 2 * ny * (nz + 1) * csize
+    octant = (nx + 1) * (ny + 1) * (nz + 1) * 8
+    return {"y_fwd": zh + yb, "x_pass": 2 * yb + octant, "x_pars2": 2 * yb + octant}[which]
+
+
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the copy-kernel
+# calibration; see the hbm_traffic summary under profiles/), valid while the kernel sources
+# hash to `src`.
+MEASURED_TRAFFIC = {
+    "y_fwd": {"bytes": 214.0e6, "src": "1483827c41771126"},
+    "x_pass": {"bytes": 416.5e6, "src": "1483827c41771126"},
+    "x_pars2": {"bytes": 382.7e6, "src": "1483827c41771126"},
+}
+
+
+def kernel_src_hash():
+    import hashlib
+    m = hashlib.sha256()
+    for f in ("regfft.h", "rfkern.inc", "fft.h", "common.h", "lines.h"):
+        with open(os.path.join(ROOT, "paper_2603_05194_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+PASSES = {  # name: (bec_time_stage selector, launches per PCG iteration, kernel)
+    "y_fwd": (5, 3, "k_rf_pad_fwd (ATKM padded y forward)"),
+    "x_pass": (0, 1, "k_rf_atkm_x (ATKM padded x pass: forward, S' multiply, inverse)"),
+    "x_pars2": (6, 1, "k_rf_atkm_x_pars (two-density padded x Parseval pass)"),
+}
 
 
 def cpu_baseline(w, gpu_iters, n_iter=2):
@@ -71,8 +102,8 @@ def cpu_baseline(w, gpu_iters, n_iter=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--quick", action="store_true", help="reduced grid (for testing the script)")
@@ -128,21 +159,27 @@ def main():
     s_per_solve = t_total / args.steps
     it_per_s = sum(iters) / t_total
 
-    # H phi applies/s and the dominant kernel, timed with HIP events on the library stream
+    # H phi applies/s and the padded passes, timed with HIP events on the library stream
     phi = steps[0]
     t_apply_ms = g.time_stage(p, phi, 2, reps=20)
     t_atkm_ms = g.time_stage(p, phi, 1, reps=20)
-    t_x_ms = g.time_stage(p, phi, 0, reps=50)
-    x_bytes = atkm_x_bytes(n, 16)
-    achieved = x_bytes / (t_x_ms * 1e-3) / 1e9
-    log(f"apply {t_apply_ms:.3f} ms, atkm {t_atkm_ms:.3f} ms, atkm x pass {t_x_ms:.3f} ms -> {achieved:.0f} GB/s")
+    t_copy_ms = g.time_stage(p, phi, 4, reps=50)
+    copy_gbs = 2 * 16 * n[0] * n[1] * n[2] / (t_copy_ms * 1e-3) / 1e9
+    kern = {}
+    for name, (which, per_iter, label) in PASSES.items():
+        ms = g.time_stage(p, phi, which, reps=50)
+        b = pass_bytes(name, n, 16)
+        kern[name] = {"kernel": label, "avg_ms": ms, "launches_per_iter": per_iter, "algorithmic_bytes": b,
+                      "achieved_GBs": b / (ms * 1e-3) / 1e9, "ms_per_iter": ms * per_iter}
+        log(f"{name}: {ms:.4f} ms x {per_iter} -> {kern[name]['achieved_GBs']:.0f} GB/s")
+    dom = max(kern, key=lambda k: kern[k]["ms_per_iter"])
+    achieved = kern[dom]["achieved_GBs"]
+    log(f"apply {t_apply_ms:.3f} ms, atkm {t_atkm_ms:.3f} ms, copy {copy_gbs:.0f} GB/s, dominant {dom}")
 
     mixed = None
     if not args.no_mixed:
         gm = bec.BecGrid(n, w.a, precision=bec.BEC_FP32)
         gm.ensure_symbol()
-        phim = guess(0)
-        rm = gm.pcg_solve(p, phim, opts)     # warm
         phim = guess(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -180,7 +217,7 @@ def main():
         "config": {"workload": f"pancake trap {n[0]}x{n[1]}x{n[2]} on [-16,16]^2x[-2,2], gamma=(1,1,20), "
                                f"beta=2000, lambda=600, n=(sin30,0,cos30), Omega=0.9; random-phase Gaussian "
                                f"guess seeds 0..{args.steps - 1}; FP64 PCG-ATKM to ||r||_inf<=1e-8",
-                   "grid": list(n), "padded": [2 * v for v in n]},
+                   "grid": list(n), "padded": [2 * v for v in n], "tol_res_inf": 1e-8},
         "iters_per_solve": iters,
         "pcg_iters_per_s": it_per_s,
         "hphi_per_s": 1e3 / t_apply_ms,
@@ -188,9 +225,13 @@ def main():
         "symbol_precompute_s": t_symbol,
         "mixed": mixed,
         "learned": None,
-        "roofline": {"bound": "hbm", "kernel": "k_atkm_x (padded x pass: forward, S' multiply, inverse)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes": x_bytes, "avg_ms": t_x_ms},
+        "roofline": {"bound": "hbm", "kernel": kern[dom]["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (MEASURED_TRAFFIC[dom]["bytes"] if MEASURED_TRAFFIC.get(dom, {}).get("src") == kernel_src_hash()
+                                 else None),
+                     "algorithmic_bytes": kern[dom]["algorithmic_bytes"], "avg_ms": kern[dom]["avg_ms"]},
+        "passes": kern,
+        "copy_GBs": copy_gbs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

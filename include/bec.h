@@ -140,9 +140,11 @@ int bec_fft3d(bec_grid g, const void* d_in, void* d_out, int dir);
 
 /* Measurement helper: runs one stage of the hot path `reps` times on the grid's stream and
  * returns the mean duration per run from HIP events (milliseconds). which = 0: the ATKM
- * padded x pass (forward, symbol multiply, inverse) on the current ATKM buffer; 1: the whole
- * ATKM potential of |phi|^2; 2: the whole H phi apply; 3: the 3-D FFT of phi (forward).
- * Needs bec_atkm_symbol for which = 0..2. Synchronises. */
+ * padded x pass (forward, symbol multiply, inverse); 1: the whole ATKM potential of |phi|^2;
+ * 2: the whole H phi apply; 3: the 3-D FFT of phi (forward); 4: a plain copy of one complex
+ * field (bandwidth calibration); 5: the ATKM padded y forward pass; 6: the two-density
+ * padded x Parseval pass of the step model. Needs bec_atkm_symbol except for 3 and 4.
+ * Synchronises. */
 int bec_time_stage(bec_grid g, const bec_params* p, const void* d_phi, int which, int reps, double* avg_ms);
 
 #ifdef __cplusplus

@@ -278,7 +278,9 @@ int pcg_phase(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi, const bec_pcg
             }
             if (hs.done) break;
             if (stall_stop) {
-                if (hs.res_inf < 0.999 * best) { best = hs.res_inf; best_it = hs.iter; polls_since = 0; }
+                // FP32 phase: leave when ||r||_inf has not dropped below 0.9x its best value
+                // for stall_window iterations (FP32 rounding floor reached)
+                if (hs.res_inf < 0.9 * best) { best = hs.res_inf; best_it = hs.iter; }
                 else if (hs.iter - best_it >= o.stall_window) break;
                 (void)polls_since;
             }
@@ -555,7 +557,7 @@ int bec_pcg_default_opts(bec_pcg_opts* o) {
     o->tau_E_ulps = 64.0;
     o->switch_res = 1e-5;
     o->check_every = 16;
-    o->stall_window = 20;
+    o->stall_window = 400;
     o->use_graph = 1;
     return BEC_OK;
 }
@@ -579,8 +581,8 @@ int bec_time_stage(bec_grid g, const bec_params* pp, const void* d_phi, int whic
     if (rc) return rc;
     Params p;
     if ((rc = validate_params(pp, p))) return rc;
-    if (!d_phi || !avg_ms || reps < 1 || which < 0 || which > 3) return fail(BEC_EINVAL, "bad arguments");
-    if (which <= 2 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    if (!d_phi || !avg_ms || reps < 1 || which < 0 || which > 6) return fail(BEC_EINVAL, "bad arguments");
+    if (which != 3 && which != 4 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
     launch_set_params(*g, p);
     if (g->precision == BEC_FP64)
         *avg_ms = time_stage<double>(*g, g->f64, p, (const cpx<double>*)d_phi, which, reps);
