@@ -23,6 +23,11 @@
  *    NULL for the default stream) and is asynchronous, except calls that return host data
  *    (bec_energy with out_on_host, bec_pcg_solve), which synchronise that stream.
  *    A handle must not be used from two threads at once.
+ *  - Batches: a grid may hold `batch` independent solves on the same box and grid (see
+ *    bec_init_grid_batched). Then every `bec_params*` argument points to `batch` parameter
+ *    sets, every field argument holds `batch` fields back to back ([batch][Nx][Ny][Nz]), and
+ *    every per-solve output (mu, energies, results) has `batch` entries. One launch per phase
+ *    serves the whole batch. bec_init_grid is the batch = 1 case.
  *  - Errors: arguments are validated before any launch; nothing throws or aborts. A HIP
  *    failure marks the handle (BEC_EHIP) and every later call on it returns BEC_EHIP.
  *    bec_last_error() gives a thread-local message for the last failing call.
@@ -92,13 +97,19 @@ const char* bec_status_string(int status);
 const char* bec_last_error(void);
 int bec_version(void);
 
-/* Workspace size in bytes for a grid and precision. */
+/* Workspace size in bytes for a grid and precision (one solve / `batch` solves). */
 int bec_workspace_bytes(const bec_grid_desc* desc, int precision, size_t* bytes);
+int bec_workspace_bytes_batched(const bec_grid_desc* desc, int precision, int batch, size_t* bytes);
 
 /* Creates a handle over a caller-owned device workspace (>= bec_workspace_bytes, 256-byte
  * aligned) on `hip_stream`. Computes nothing yet. */
 int bec_init_grid(const bec_grid_desc* desc, int precision, void* d_workspace, size_t ws_bytes,
                   void* hip_stream, bec_grid* out);
+/* Same for a batch of 1..65535 independent solves on one box and grid (parameter sweeps,
+ * training-set generation). The truncated-kernel symbol is shared by the batch. */
+int bec_init_grid_batched(const bec_grid_desc* desc, int precision, int batch, void* d_workspace,
+                          size_t ws_bytes, void* hip_stream, bec_grid* out);
+int bec_grid_batch(bec_grid g);
 int bec_destroy_grid(bec_grid g);
 
 /* Truncated-kernel Fourier integral U_k of U = 1/(4 pi |y|) over the twofold box (Sec. 2.2,
@@ -132,6 +143,12 @@ int bec_energy(bec_grid g, const bec_params* p, const void* d_phi, bec_energies*
  * struct is filled in all three cases). Synchronises. */
 int bec_pcg_solve(bec_grid g, const bec_params* p, void* d_phi, const bec_pcg_opts* opts,
                   bec_pcg_result* h_result);
+/* Algorithm 1 for every solve of a batched grid at once: `p` holds `batch` parameter sets,
+ * d_phi `batch` guesses, h_results `batch` results. Finished solves stop costing work (their
+ * blocks return at once); the call returns when all are done. Returns the worst status
+ * (BEC_ENUMERIC over BEC_ENOTCONV over BEC_OK). */
+int bec_pcg_solve_batched(bec_grid g, const bec_params* p, void* d_phi, const bec_pcg_opts* opts,
+                          bec_pcg_result* h_results);
 int bec_pcg_default_opts(bec_pcg_opts* opts);
 
 /* 3-D C2C FFT on the N grid (unnormalised; dir = -1 forward exp(-2 pi i jk/N), +1 inverse),

@@ -62,6 +62,12 @@ _SIGS = {
     "bec_last_error": (C.c_char_p, []),
     "bec_version": (C.c_int, []),
     "bec_workspace_bytes": (C.c_int, [C.POINTER(bec_grid_desc), C.c_int, C.POINTER(C.c_size_t)]),
+    "bec_workspace_bytes_batched": (C.c_int, [C.POINTER(bec_grid_desc), C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "bec_init_grid_batched": (C.c_int, [C.POINTER(bec_grid_desc), C.c_int, C.c_int, C.c_void_p, C.c_size_t,
+                                        C.c_void_p, C.POINTER(C.c_void_p)]),
+    "bec_grid_batch": (C.c_int, [C.c_void_p]),
+    "bec_pcg_solve_batched": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.POINTER(bec_pcg_opts),
+                                        C.POINTER(bec_pcg_result)]),
     "bec_init_grid": (C.c_int, [C.POINTER(bec_grid_desc), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
                                 C.POINTER(C.c_void_p)]),
     "bec_destroy_grid": (C.c_int, [C.c_void_p]),
@@ -106,10 +112,24 @@ def bec_workspace_bytes(desc: bec_grid_desc, precision: int) -> int:
     return out.value
 
 
+def bec_workspace_bytes_batched(desc: bec_grid_desc, precision: int, batch: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib().bec_workspace_bytes_batched(C.byref(desc), precision, batch, C.byref(out)),
+           "bec_workspace_bytes_batched")
+    return out.value
+
+
 def bec_init_grid(desc, precision, d_ws, ws_bytes, stream):
     h = C.c_void_p()
     _check(_lib().bec_init_grid(C.byref(desc), precision, C.c_void_p(d_ws), ws_bytes, C.c_void_p(stream),
                                 C.byref(h)), "bec_init_grid")
+    return h
+
+
+def bec_init_grid_batched(desc, precision, batch, d_ws, ws_bytes, stream):
+    h = C.c_void_p()
+    _check(_lib().bec_init_grid_batched(C.byref(desc), precision, batch, C.c_void_p(d_ws), ws_bytes,
+                                        C.c_void_p(stream), C.byref(h)), "bec_init_grid_batched")
     return h
 
 
@@ -122,19 +142,26 @@ def bec_atkm_symbol(h, d_out=None):
 
 
 def bec_dipolar(h, params, d_phi, d_Phi):
-    _check(_lib().bec_dipolar(h, C.byref(params), C.c_void_p(d_phi), C.c_void_p(d_Phi)), "bec_dipolar")
+    _check(_lib().bec_dipolar(h, _params_arg(params), C.c_void_p(d_phi), C.c_void_p(d_Phi)), "bec_dipolar")
 
 
 def bec_apply_H(h, params, d_phi, d_hphi, d_Phi=None, d_mu=None):
-    _check(_lib().bec_apply_H(h, C.byref(params), C.c_void_p(d_phi), C.c_void_p(d_hphi),
+    _check(_lib().bec_apply_H(h, _params_arg(params), C.c_void_p(d_phi), C.c_void_p(d_hphi),
                               C.c_void_p(d_Phi) if d_Phi else None, C.c_void_p(d_mu) if d_mu else None),
            "bec_apply_H")
 
 
-def bec_energy(h, params, d_phi) -> bec_energies:
-    out = bec_energies()
-    _check(_lib().bec_energy(h, C.byref(params), C.c_void_p(d_phi), C.byref(out), 1), "bec_energy")
-    return out
+def _params_arg(params):
+    """One bec_params or a ctypes array of them (batched grids)."""
+    if isinstance(params, bec_params):
+        return C.byref(params)
+    return C.cast(params, C.POINTER(bec_params))
+
+
+def bec_energy(h, params, d_phi, batch=1):
+    out = (bec_energies * batch)()
+    _check(_lib().bec_energy(h, _params_arg(params), C.c_void_p(d_phi), C.cast(out, C.c_void_p), 1), "bec_energy")
+    return out[0] if batch == 1 else list(out)
 
 
 def bec_pcg_default_opts() -> bec_pcg_opts:
@@ -151,13 +178,21 @@ def bec_pcg_solve(h, params, d_phi, opts=None) -> bec_pcg_result:
     return res
 
 
+def bec_pcg_solve_batched(h, params_array, d_phi, batch, opts=None):
+    res = (bec_pcg_result * batch)()
+    rc = _lib().bec_pcg_solve_batched(h, _params_arg(params_array), C.c_void_p(d_phi),
+                                      C.byref(opts) if opts is not None else None, res)
+    _check(rc, "bec_pcg_solve_batched", ok=(BEC_OK, BEC_ENOTCONV, BEC_ENUMERIC))
+    return list(res)
+
+
 def bec_fft3d(h, d_in, d_out, direction):
     _check(_lib().bec_fft3d(h, C.c_void_p(d_in), C.c_void_p(d_out), direction), "bec_fft3d")
 
 
 def bec_time_stage(h, params, d_phi, which, reps) -> float:
     ms = C.c_double(0.0)
-    _check(_lib().bec_time_stage(h, C.byref(params), C.c_void_p(d_phi), which, reps, C.byref(ms)), "bec_time_stage")
+    _check(_lib().bec_time_stage(h, _params_arg(params), C.c_void_p(d_phi), which, reps, C.byref(ms)), "bec_time_stage")
     return ms.value
 
 
@@ -182,20 +217,22 @@ def make_params(gamma, beta, lam, ndip, omega) -> bec_params:
 class BecGrid:
     """Owns a torch-allocated workspace and a library handle for one box/grid."""
 
-    def __init__(self, n, a, precision=BEC_FP64, device="cuda", stream=None):
+    def __init__(self, n, a, precision=BEC_FP64, device="cuda", stream=None, batch=1):
         import torch
         self.torch = torch
         self.n, self.a = tuple(int(v) for v in n), tuple(float(v) for v in a)
         self.precision = precision
+        self.batch = int(batch)
         self.desc = make_desc(self.n, self.a)
-        self.ws_bytes = bec_workspace_bytes(self.desc, precision)
+        self.ws_bytes = bec_workspace_bytes_batched(self.desc, precision, self.batch)
         self.device = torch.device(device)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         off = (-base) % 256
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
-        self.handle = bec_init_grid(self.desc, precision, base + off, self.ws_bytes, s.cuda_stream)
+        self.handle = bec_init_grid_batched(self.desc, precision, self.batch, base + off, self.ws_bytes,
+                                            s.cuda_stream)
         self._symbol = False
 
     def close(self):
@@ -258,6 +295,25 @@ class BecGrid:
                     mu.data_ptr())
         return (h, mu, Phi) if want_Phi else (h, mu)
 
+    def apply_H_batched(self, params_list, phis):
+        """H phi for every solve: phis is a contiguous [batch, Nx, Ny, Nz] tensor."""
+        assert len(params_list) == self.batch and tuple(phis.shape) == (self.batch,) + self.n
+        assert phis.is_contiguous() and phis.dtype == self.cdtype
+        if any(p.lambda_ != 0.0 for p in params_list):
+            self.ensure_symbol()
+        arr = (bec_params * self.batch)(*params_list)
+        h = self.torch.empty_like(phis)
+        mu = self.torch.empty(self.batch, dtype=self.torch.float64, device=self.device)
+        bec_apply_H(self.handle, arr, phis.data_ptr(), h.data_ptr(), None, mu.data_ptr())
+        return h, mu
+
+    def energy_batched(self, params_list, phis):
+        assert len(params_list) == self.batch and tuple(phis.shape) == (self.batch,) + self.n
+        if any(p.lambda_ != 0.0 for p in params_list):
+            self.ensure_symbol()
+        arr = (bec_params * self.batch)(*params_list)
+        return [e.as_dict() for e in bec_energy(self.handle, arr, phis.data_ptr(), self.batch)]
+
     def energy(self, params, phi) -> dict:
         if params.lambda_ != 0.0:
             self.ensure_symbol()
@@ -271,5 +327,16 @@ class BecGrid:
     def pcg_solve(self, params, phi, opts=None):
         if params.lambda_ != 0.0:
             self.ensure_symbol()
+        assert self.batch == 1
         assert phi.is_contiguous() and phi.dtype == self.torch.complex128 and tuple(phi.shape) == self.n
         return bec_pcg_solve(self.handle, params, phi.data_ptr(), opts)
+
+    def pcg_solve_batched(self, params_list, phis, opts=None):
+        """params_list: `batch` bec_params; phis: contiguous complex128 tensor [batch, Nx, Ny, Nz]."""
+        assert len(params_list) == self.batch
+        if any(p.lambda_ != 0.0 for p in params_list):
+            self.ensure_symbol()
+        assert phis.is_contiguous() and phis.dtype == self.torch.complex128
+        assert tuple(phis.shape) == (self.batch,) + self.n
+        arr = (bec_params * self.batch)(*params_list)
+        return bec_pcg_solve_batched(self.handle, arr, phis.data_ptr(), self.batch, opts)

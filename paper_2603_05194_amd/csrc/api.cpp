@@ -50,6 +50,8 @@ int validate_desc(const bec_grid_desc* d) {
 
 int validate_params(const bec_params* p, Params& out) {
     if (!p) return fail(BEC_EINVAL, "params is NULL");
+    if (!std::isfinite(p->n[0]) || !std::isfinite(p->n[1]) || !std::isfinite(p->n[2]))
+        return fail(BEC_EINVAL, "non-finite dipole axis");
     const double nn = std::sqrt(p->n[0] * p->n[0] + p->n[1] * p->n[1] + p->n[2] * p->n[2]);
     if (!(std::fabs(nn - 1.0) <= 1e-12)) return fail(BEC_EINVAL, "dipole axis must be a unit vector");
     for (int i = 0; i < 3; ++i) {
@@ -78,11 +80,10 @@ std::vector<int> factor(int n) {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t state, partials, uhat, symscr, tw64, tw32, f64, f32, total;
-    size_t partials_cap, symscr_doubles;
+    size_t state, params, stop, partials, uhat, symscr, tw64, tw32, f64, f32, total;
+    long part_stride;
+    size_t symscr_doubles;
 };
-
-int tiles_of(const Geo& g) { return g.ntiles; }
 
 Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
     Geo g;
@@ -118,34 +119,39 @@ Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
     return g;
 }
 
-Layout layout(const int n[3], int precision) {
+Layout layout(const int n[3], int precision, int batch) {
     Layout L;
     const size_t N = (size_t)n[0] * n[1] * n[2];
     const size_t Nz1 = (size_t)n[0] * n[1] * (n[2] + 1);
     const size_t Ny2 = (size_t)n[0] * 2 * n[1] * (n[2] + 1);
-    // partials: generous bound on tiles x slots of one reducing kernel
+    // partial sums of one reducing kernel: at most (blocks of the largest pass) x slots; the
+    // register-FFT passes use fewer lines per block than the generic ones at small N, so bound
+    // by one block per column as well
     size_t maxt = 0;
-    maxt = std::max(maxt, (size_t)make_geo(0, n[0], 2 * n[1], n[2] + 1, 2 * n[0], 1).ntiles);
-    maxt = std::max(maxt, (size_t)make_geo(0, n[0], n[1], n[2], n[0], 0).ntiles);
-    maxt = std::max(maxt, (size_t)make_geo(1, n[0], n[1], n[2], n[1], 0).ntiles);
-    maxt = std::max(maxt, (size_t)make_geo(2, n[0], n[1], n[2], n[2], 0).ntiles);
-    maxt = std::max(maxt, N / kThreads + 1);
-    L.partials_cap = maxt * kMaxRed + 1024;
+    maxt = std::max(maxt, (size_t)2 * n[1] * (n[2] + 1));          // padded x pass, >= 1 column per block
+    maxt = std::max(maxt, (size_t)n[1] * n[2]);                    // N-grid x pass
+    maxt = std::max(maxt, (size_t)n[0] * (n[2] + 1));              // y passes
+    maxt = std::max(maxt, (size_t)n[0] * n[1]);                    // z passes
+    maxt = std::max(maxt, (size_t)kRedBlocks);
+    L.part_stride = (long)(maxt * 12 + 64);
     const int ms = 651;
     size_t sd = 2 * ms;
     for (int d = 0; d < 3; ++d) sd += (size_t)ms * (n[d] + 1) + 2 * ((size_t)std::ceil(M_PI * n[d] / 2.0) + 80);
     L.symscr_doubles = sd;
     size_t tw = 0;
     for (int d = 0; d < 3; ++d) tw += al((size_t)n[d] * 16) + al((size_t)2 * n[d] * 16);
+    const size_t B = (size_t)batch;
     size_t off = 0;
-    L.state = off; off += al(sizeof(DevState));
-    L.partials = off; off += al(L.partials_cap * sizeof(double));
+    L.state = off; off += al(B * sizeof(DevState));
+    L.params = off; off += al(B * sizeof(Params));
+    L.stop = off; off += al(B * sizeof(int));
+    L.partials = off; off += al(B * L.part_stride * sizeof(double));
     L.uhat = off; off += al((size_t)(n[0] + 1) * (n[1] + 1) * (n[2] + 1) * sizeof(double));
     L.symscr = off; off += al(sd * sizeof(double));
     L.tw64 = off; off += tw;
-    L.tw32 = off; off += precision ? tw / 2 + 6 * 256 : 0;
+    L.tw32 = off; off += precision ? tw : 0;
     auto fields_bytes = [&](size_t cs) {
-        return 8 * al(N * 2 * cs) + 2 * al(N * cs) + 2 * al(Nz1 * 2 * cs) + 2 * al(Ny2 * 2 * cs);
+        return 8 * al(B * N * 2 * cs) + 2 * al(B * N * cs) + 2 * al(B * Nz1 * 2 * cs) + 2 * al(B * Ny2 * 2 * cs);
     };
     L.f64 = off; off += fields_bytes(8);
     L.f32 = off; off += precision ? fields_bytes(4) : 0;
@@ -153,10 +159,11 @@ Layout layout(const int n[3], int precision) {
     return L;
 }
 
-template <typename R> void carve_fields(Fields<R>& f, char*& p, const int n[3]) {
-    const size_t N = (size_t)n[0] * n[1] * n[2];
-    const size_t Nz1 = (size_t)n[0] * n[1] * (n[2] + 1);
-    const size_t Ny2 = (size_t)n[0] * 2 * n[1] * (n[2] + 1);
+template <typename R> void carve_fields(Fields<R>& f, char*& p, const int n[3], int batch) {
+    const size_t B = (size_t)batch;
+    const size_t N = B * n[0] * n[1] * n[2];
+    const size_t Nz1 = B * n[0] * n[1] * (n[2] + 1);
+    const size_t Ny2 = B * n[0] * 2 * n[1] * (n[2] + 1);
     auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
     f.hphi = (cpx<R>*)take(N * sizeof(cpx<R>));
     f.acc = (cpx<R>*)take(N * sizeof(cpx<R>));
@@ -217,82 +224,114 @@ int check_launch(Grid* g, const char* where) {
     return BEC_OK;
 }
 
-// ------------------------------------------------------------------ PCG driver
-// Runs Algorithm 1 with all scalar decisions on the device. The host enqueues iterations
-// (eagerly for the first two, then as a captured two-iteration HIP graph) on a private
-// non-blocking stream and reads the device state every check_every iterations.
-struct HostPoll { int done, status, iter; double res; };
+// Validates `batch` parameter sets and uploads them to the device state of the grid.
+int upload_params(Grid& g, const bec_params* pp) {
+    if (!pp) return fail(BEC_EINVAL, "params is NULL");
+    std::vector<Params> ps(g.batch);
+    bool any = false;
+    for (int b = 0; b < g.batch; ++b) {
+        int rc = validate_params(pp + b, ps[b]);
+        if (rc) return rc;
+        any = any || ps[b].lam != 0.0;
+    }
+    if (any && !g.have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    hipError_t e = hipMemcpyAsync(g.dparams, ps.data(), ps.size() * sizeof(Params), hipMemcpyHostToDevice, g.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+    if (e != hipSuccess) return hip_fail(&g, e, "params upload");
+    g.lam_any = any;
+    launch_set_params(g);
+    return check_launch(&g, "set params");
+}
 
-int read_state(Grid& g, DevState& hs) {
-    hipError_t e = hipMemcpyAsync(&hs, g.st, sizeof(DevState), hipMemcpyDeviceToHost, g.stream);
+int read_states(Grid& g, std::vector<DevState>& hs) {
+    hs.resize(g.batch);
+    hipError_t e = hipMemcpyAsync(hs.data(), g.st, g.batch * sizeof(DevState), hipMemcpyDeviceToHost, g.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
     if (e != hipSuccess) return hip_fail(&g, e, "state readback");
     return BEC_OK;
 }
 
+// ------------------------------------------------------------------ PCG driver
+// Runs Algorithm 1 for every solve of the batch with all scalar decisions on the device. The
+// host enqueues iterations (eagerly for the first two, then as a captured two-iteration HIP
+// graph) on a private non-blocking stream and reads the device states every check_every
+// iterations; it stops when every solve is done. In the FP32 phase it also stops solves whose
+// ||r||_inf has not dropped below 0.9x its best for stall_window iterations.
 template <typename R>
-int pcg_phase(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi, const bec_pcg_opts& o, bool stall_stop,
-              DevState& hs) {
+int pcg_phase(Grid& g, cpx<R>* phi, const bec_pcg_opts& o, bool stall_stop, std::vector<DevState>& hs) {
     int rc;
-    launch_pcg_start<R>(g, f, p, phi);
+    launch_pcg_start<R>(g, phi);
     if ((rc = check_launch(&g, "pcg start"))) return rc;
     const int every = o.check_every;
     long it = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    double best = 1e300;
-    long best_it = 0;
-    int polls_since = 0;
+    std::vector<double> best(g.batch, 1e300);
+    std::vector<long> best_it(g.batch, 0);
+    std::vector<int> stop(g.batch, 0);
     const char* prog = std::getenv("BEC_PROGRESS");
     const double prog_every = prog ? std::atof(prog) : 0.0;
-    double last_print = 0.0;
     auto now = []() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
-    if (prog_every > 0) last_print = now();
+    double last_print = prog_every > 0 ? now() : 0.0;
     for (;;) {
         if (o.use_graph && it >= 2 && (it & 1) == 0) {
             if (!exec) {
                 hipError_t e = hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) return hip_fail(&g, e, "begin capture");
-                launch_pcg_iteration<R>(g, f, p, phi, 0);
-                launch_pcg_iteration<R>(g, f, p, phi, 1);
+                if (e != hipSuccess) { rc = hip_fail(&g, e, "begin capture"); break; }
+                launch_pcg_iteration<R>(g, phi, 0);
+                launch_pcg_iteration<R>(g, phi, 1);
                 e = hipStreamEndCapture(g.stream, &graph);
-                if (e != hipSuccess) return hip_fail(&g, e, "end capture");
+                if (e != hipSuccess) { rc = hip_fail(&g, e, "end capture"); break; }
                 e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                if (e != hipSuccess) return hip_fail(&g, e, "graph instantiate");
+                if (e != hipSuccess) { rc = hip_fail(&g, e, "graph instantiate"); break; }
             }
             hipError_t e = hipGraphLaunch(exec, g.stream);
-            if (e != hipSuccess) return hip_fail(&g, e, "graph launch");
+            if (e != hipSuccess) { rc = hip_fail(&g, e, "graph launch"); break; }
             it += 2;
         } else {
-            launch_pcg_iteration<R>(g, f, p, phi, (int)(it & 1));
+            launch_pcg_iteration<R>(g, phi, (int)(it & 1));
             it += 1;
         }
         if ((rc = check_launch(&g, "pcg iteration"))) break;
         if (it % every == 0 || it < 2) {
-            if ((rc = read_state(g, hs))) break;
+            if ((rc = read_states(g, hs))) break;
+            bool all = true;
+            double rmin = 1e300, rmax = 0.0;
+            int ndone = 0;
+            bool new_stop = false;
+            for (int b = 0; b < g.batch; ++b) {
+                const DevState& S = hs[b];
+                if (S.done) { ++ndone; continue; }
+                all = false;
+                rmin = std::min(rmin, S.res_inf);
+                rmax = std::max(rmax, S.res_inf);
+                if (stall_stop) {
+                    if (S.res_inf < 0.9 * best[b]) { best[b] = S.res_inf; best_it[b] = S.iter; }
+                    else if (S.iter - best_it[b] >= o.stall_window && !stop[b]) { stop[b] = 1; new_stop = true; }
+                }
+            }
             if (prog_every > 0 && now() - last_print >= prog_every) {
-                std::fprintf(stderr, "[bec] %s iter %d res %.3e E %.15f\n", sizeof(R) == 4 ? "fp32" : "fp64", hs.iter,
-                             hs.res_inf, hs.E);
+                std::fprintf(stderr, "[bec] %s iter %d done %d/%d res %.3e..%.3e E0 %.15f\n", sizeof(R) == 4 ? "fp32" : "fp64",
+                             hs[0].iter, ndone, g.batch, rmin, rmax, hs[0].E);
                 std::fflush(stderr);
                 last_print = now();
             }
-            if (hs.done) break;
-            if (stall_stop) {
-                // FP32 phase: leave when ||r||_inf has not dropped below 0.9x its best value
-                // for stall_window iterations (FP32 rounding floor reached)
-                if (hs.res_inf < 0.9 * best) { best = hs.res_inf; best_it = hs.iter; }
-                else if (hs.iter - best_it >= o.stall_window) break;
-                (void)polls_since;
+            if (all) break;
+            if (new_stop) {
+                hipError_t e = hipMemcpyAsync(g.dstop, stop.data(), g.batch * sizeof(int), hipMemcpyHostToDevice, g.stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+                if (e != hipSuccess) { rc = hip_fail(&g, e, "stop flags"); break; }
+                launch_ctl_stop(g);
             }
         }
     }
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
     if (rc) return rc;
-    return read_state(g, hs);
+    return read_states(g, hs);
 }
 
-int pcg_solve(Grid& g, const Params& p, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* res) {
+int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* res) {
     hipStream_t user = g.stream;
     hipStream_t ps = nullptr;
     hipEvent_t ev = nullptr;
@@ -302,64 +341,67 @@ int pcg_solve(Grid& g, const Params& p, cpx<double>* phi, const bec_pcg_opts& o,
     if (e == hipSuccess) e = hipStreamWaitEvent(ps, ev, 0);
     if (e != hipSuccess) return hip_fail(&g, e, "solve stream");
     g.stream = ps;
-    const long N = (long)g.n[0] * g.n[1] * g.n[2];
+    const size_t NB = (size_t)g.n[0] * g.n[1] * g.n[2] * g.batch;
     CtlOpts co;
     co.tol_res = o.tol_res_inf; co.tol_step = o.tol_step_inf; co.t_default = o.t_default; co.tau_ulps = o.tau_E_ulps;
     co.dbg_t = o.debug_t; co.dbg_c2 = o.debug_c2; co.max_iter = o.max_iter; co.max_halv = o.max_halvings;
-    co.dbg_flags = o.debug_flags; co.fp32 = g.precision;
-    DevState hs;
-    std::memset(&hs, 0, sizeof(hs));
+    co.dbg_flags = o.debug_flags; co.fp32 = 0;
+    std::vector<DevState> hs;
     int rc = BEC_OK;
-    int fp32_iters = 0;
-    // clear reductions and the CG memory buffers once (outside any captured graph)
-    e = hipMemsetAsync(g.st->red, 0, sizeof(g.st->red), g.stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.f64.p, 0, N * sizeof(cpx<double>), g.stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.f64.r1, 0, N * sizeof(cpx<double>), g.stream);
+    // clear reductions, CG memory buffers and stop flags once (outside any captured graph)
+    e = hipMemsetAsync(g.dstop, 0, g.batch * sizeof(int), g.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.f64.p, 0, NB * sizeof(cpx<double>), g.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.f64.r1, 0, NB * sizeof(cpx<double>), g.stream);
     if (e != hipSuccess) rc = hip_fail(&g, e, "solve init");
     if (!rc && g.precision == BEC_FP32) {
-        // FP32 bulk phase: stop at ||r||_inf <= switch_res or when the residual stalls
+        // FP32 bulk phase: stop at ||r||_inf <= switch_res or when the residual stalls. The
+        // trial energies are FP64 polynomials of FP64 sums, so the energy test keeps its FP64
+        // slack (an FP32-sized slack accepts energy increases and the phase never settles).
         co.tol_res = std::max(o.switch_res, o.tol_res_inf);
+        co.fp32 = 0;
         launch_ctl_init(g, co);
-        e = hipMemsetAsync(g.f32.p, 0, N * sizeof(cpx<float>), g.stream);
-        if (e == hipSuccess) e = hipMemsetAsync(g.f32.r1, 0, N * sizeof(cpx<float>), g.stream);
+        e = hipMemsetAsync(g.f32.p, 0, NB * sizeof(cpx<float>), g.stream);
+        if (e == hipSuccess) e = hipMemsetAsync(g.f32.r1, 0, NB * sizeof(cpx<float>), g.stream);
         if (e != hipSuccess) rc = hip_fail(&g, e, "solve init");
         if (!rc) {
             launch_to_f32(g, phi, g.f32.phi);
-            rc = pcg_phase<float>(g, g.f32, p, g.f32.phi, o, true, hs);
+            rc = pcg_phase<float>(g, g.f32.phi, o, true, hs);
         }
         if (!rc) {
-            fp32_iters = hs.iter;
-            if (hs.status == BEC_ENUMERIC) {
-                // keep the caller's guess untouched; fall through to the FP64 phase from it
-            } else {
-                launch_to_f64_normalized(g, g.f32.phi, phi);
-            }
-            launch_ctl_phase(g, o.tol_res_inf, o.max_iter);
+            // reopen the solves first: the normalisation kernels skip solves marked done
+            launch_ctl_phase(g, o.tol_res_inf, o.max_iter, o.tau_E_ulps, 2.220446049250313e-16);
+            launch_to_f64_normalized(g, g.f32.phi, phi);
             rc = check_launch(&g, "phase switch");
         }
-        if (!rc) rc = pcg_phase<double>(g, g.f64, p, phi, o, false, hs);
+        if (!rc) rc = pcg_phase<double>(g, phi, o, false, hs);
     } else if (!rc) {
         launch_ctl_init(g, co);
-        rc = pcg_phase<double>(g, g.f64, p, phi, o, false, hs);
+        rc = pcg_phase<double>(g, phi, o, false, hs);
     }
     hipStreamSynchronize(ps);
     g.stream = user;
     hipEventDestroy(ev);
     hipStreamDestroy(ps);
     if (rc) return rc;
-    res->status = hs.status == 0 ? BEC_OK : hs.status;
-    res->iters = hs.iter;
-    res->halvings = hs.halvings;
-    res->psd_resets = hs.resets;
-    res->forced_accepts = hs.forced;
-    res->fp32_iters = fp32_iters;
-    res->res_inf = hs.res_inf;
-    res->step_inf = hs.step_inf;
-    res->e.E = hs.E; res->e.Ekin = hs.Ekin; res->e.Epot = hs.Epot; res->e.Eint = hs.Eint;
-    res->e.Edip = hs.Edip; res->e.Erot = hs.Erot; res->e.mu = hs.mu; res->e.mass = hs.mass;
-    res->e.virial = 2 * hs.Ekin - 2 * hs.Epot + 3 * hs.Eint + 3 * hs.Edip;
-    if (res->status != BEC_OK) g_last_error = bec_status_string(res->status);
-    return res->status;
+    int worst = BEC_OK;
+    for (int b = 0; b < g.batch; ++b) {
+        const DevState& S = hs[b];
+        bec_pcg_result& r = res[b];
+        r.status = S.status == 0 ? BEC_OK : S.status;
+        r.iters = S.iter;
+        r.halvings = S.halvings;
+        r.psd_resets = S.resets;
+        r.forced_accepts = S.forced;
+        r.fp32_iters = g.precision == BEC_FP32 ? S.fp32_iters : 0;
+        r.res_inf = S.res_inf;
+        r.step_inf = S.step_inf;
+        r.e.E = S.E; r.e.Ekin = S.Ekin; r.e.Epot = S.Epot; r.e.Eint = S.Eint;
+        r.e.Edip = S.Edip; r.e.Erot = S.Erot; r.e.mu = S.mu; r.e.mass = S.mass;
+        r.e.virial = 2 * S.Ekin - 2 * S.Epot + 3 * S.Eint + 3 * S.Edip;
+        if (r.status == BEC_ENUMERIC || (r.status == BEC_ENOTCONV && worst == BEC_OK)) worst = r.status;
+    }
+    if (worst != BEC_OK) g_last_error = bec_status_string(worst);
+    return worst;
 }
 
 }  // namespace
@@ -381,24 +423,31 @@ const char* bec_status_string(int s) {
 
 const char* bec_last_error(void) { return g_last_error.c_str(); }
 
-int bec_version(void) { return 1; }
+int bec_version(void) { return 2; }
 
-int bec_workspace_bytes(const bec_grid_desc* desc, int precision, size_t* bytes) {
+int bec_workspace_bytes_batched(const bec_grid_desc* desc, int precision, int batch, size_t* bytes) {
     int rc = validate_desc(desc);
     if (rc) return rc;
     if (!bytes) return fail(BEC_EINVAL, "bytes is NULL");
     if (precision != BEC_FP64 && precision != BEC_FP32) return fail(BEC_EINVAL, "bad precision");
-    *bytes = layout(desc->n, precision).total;
+    if (batch < 1 || batch > 65535) return fail(BEC_EINVAL, "batch must be in [1, 65535]");
+    *bytes = layout(desc->n, precision, batch).total;
     return BEC_OK;
 }
 
-int bec_init_grid(const bec_grid_desc* desc, int precision, void* d_ws, size_t ws_bytes, void* stream, bec_grid* out) {
+int bec_workspace_bytes(const bec_grid_desc* desc, int precision, size_t* bytes) {
+    return bec_workspace_bytes_batched(desc, precision, 1, bytes);
+}
+
+int bec_init_grid_batched(const bec_grid_desc* desc, int precision, int batch, void* d_ws, size_t ws_bytes,
+                          void* stream, bec_grid* out) {
     int rc = validate_desc(desc);
     if (rc) return rc;
     if (!out || !d_ws) return fail(BEC_EINVAL, "NULL workspace or output handle");
     if (precision != BEC_FP64 && precision != BEC_FP32) return fail(BEC_EINVAL, "bad precision");
+    if (batch < 1 || batch > 65535) return fail(BEC_EINVAL, "batch must be in [1, 65535]");
     if (((uintptr_t)d_ws) & 255) return fail(BEC_EINVAL, "workspace must be 256-byte aligned");
-    Layout L = layout(desc->n, precision);
+    Layout L = layout(desc->n, precision, batch);
     if (ws_bytes < L.total) return fail(BEC_ENOMEM, "workspace smaller than bec_workspace_bytes");
     bec_grid g = new bec_grid_s();
     for (int i = 0; i < 3; ++i) {
@@ -408,45 +457,52 @@ int bec_init_grid(const bec_grid_desc* desc, int precision, void* d_ws, size_t w
     }
     g->h3 = g->h[0] * g->h[1] * g->h[2];
     g->precision = precision;
+    g->batch = batch;
     g->stream = (hipStream_t)stream;
     g->ws = (char*)d_ws;
     g->ws_bytes = ws_bytes;
     g->st = (DevState*)(g->ws + L.state);
-    g->done_flag = &g->st->done;
+    g->dparams = (Params*)(g->ws + L.params);
+    g->dstop = (int*)(g->ws + L.stop);
     g->partials = (double*)(g->ws + L.partials);
-    g->partials_cap = L.partials_cap;
+    g->part_stride = L.part_stride;
     g->uhat = (double*)(g->ws + L.uhat);
     g->sym_scratch = (double*)(g->ws + L.symscr);
     g->sym_scratch_bytes = L.symscr_doubles * sizeof(double);
     char* p = g->ws + L.f64;
-    carve_fields<double>(g->f64, p, g->n);
+    carve_fields<double>(g->f64, p, g->n, batch);
     if (precision) {
         p = g->ws + L.f32;
-        carve_fields<float>(g->f32, p, g->n);
+        carve_fields<float>(g->f32, p, g->n, batch);
     }
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
     g->gz = make_geo(2, nx, ny, nz, nz, 0);
     g->gy = make_geo(1, nx, ny, nz, ny, 0);
     g->gx = make_geo(0, nx, ny, nz, nx, 0);
     g->g_ay = make_geo(1, nx, ny, nz + 1, 2 * ny, 0);
-    g->g_ayi = g->g_ay;
     g->g_ax = make_geo(0, nx, 2 * ny, nz + 1, 2 * nx, 0);
     g->g_ax2 = make_geo(0, nx, 2 * ny, nz + 1, 2 * nx, 1);
     g->zf_L = std::max(1, kTileElems / (2 * nz));
-    if (const char* e = std::getenv("BEC_GENERIC_FFT")) g->use_rf = std::atoi(e) ? 0 : 1;
-    g->zf2_L = g->zf_L;
-    g->zi_L = g->zf_L;
+    const long N = (long)nx * ny * nz;
+    g->bt64 = Bat{N, (long)nx * ny * (nz + 1), (long)nx * 2 * ny * (nz + 1), L.part_stride};
+    g->bt32 = g->bt64;
+    if (const char* ev = std::getenv("BEC_GENERIC_FFT")) g->use_rf = std::atoi(ev) ? 0 : 1;
     if ((rc = make_plans<double>(*g, g->f64, g->ws + L.tw64))) { delete g; return rc; }
     if (precision && (rc = make_plans<float>(*g, g->f32, g->ws + L.tw32))) { delete g; return rc; }
-    hipError_t e = hipMemsetAsync(g->st, 0, sizeof(DevState), g->stream);
+    hipError_t e = hipMemsetAsync(g->st, 0, batch * sizeof(DevState), g->stream);
     if (e != hipSuccess) { int r2 = hip_fail(g, e, "init state"); delete g; return r2; }
     *out = g;
     return BEC_OK;
 }
 
+int bec_init_grid(const bec_grid_desc* desc, int precision, void* d_ws, size_t ws_bytes, void* stream, bec_grid* out) {
+    return bec_init_grid_batched(desc, precision, 1, d_ws, ws_bytes, stream, out);
+}
+
+int bec_grid_batch(bec_grid g) { return g ? g->batch : 0; }
+
 int bec_destroy_grid(bec_grid g) {
     if (!g) return BEC_OK;
-    if (g->graph) hipGraphExecDestroy(g->graph);
     delete g;
     return BEC_OK;
 }
@@ -469,36 +525,34 @@ int bec_atkm_symbol(bec_grid g, double* d_out) {
 int bec_dipolar(bec_grid g, const bec_params* pp, const void* d_phi, void* d_Phi) {
     int rc = check_grid(g);
     if (rc) return rc;
-    Params p;
-    if ((rc = validate_params(pp, p))) return rc;
     if (!d_phi || !d_Phi) return fail(BEC_EINVAL, "NULL field pointer");
     if (!g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    if ((rc = upload_params(*g, pp))) return rc;
     if (g->precision == BEC_FP64)
-        launch_atkm<double>(*g, g->f64, p, (const cpx<double>*)d_phi, (double*)d_Phi, nullptr);
+        launch_atkm<double>(*g, (const cpx<double>*)d_phi, (double*)d_Phi);
     else
-        launch_atkm<float>(*g, g->f32, p, (const cpx<float>*)d_phi, (float*)d_Phi, nullptr);
+        launch_atkm<float>(*g, (const cpx<float>*)d_phi, (float*)d_Phi);
     return check_launch(g, "dipolar");
 }
 
 int bec_apply_H(bec_grid g, const bec_params* pp, const void* d_phi, void* d_hphi, void* d_Phi, double* d_mu) {
     int rc = check_grid(g);
     if (rc) return rc;
-    Params p;
-    if ((rc = validate_params(pp, p))) return rc;
     if (!d_phi || !d_hphi) return fail(BEC_EINVAL, "NULL field pointer");
     if (d_phi == d_hphi) return fail(BEC_EINVAL, "d_hphi must not alias d_phi");
-    if (p.lam != 0.0 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
-    launch_set_params(*g, p);
+    if ((rc = upload_params(*g, pp))) return rc;
     if (g->precision == BEC_FP64) {
         double* Phi = d_Phi ? (double*)d_Phi : g->f64.Phi;
-        launch_apply<double>(*g, g->f64, p, (const cpx<double>*)d_phi, (cpx<double>*)d_hphi, Phi, nullptr);
+        launch_apply<double>(*g, (const cpx<double>*)d_phi, (cpx<double>*)d_hphi, Phi);
     } else {
         float* Phi = d_Phi ? (float*)d_Phi : g->f32.Phi;
-        launch_apply<float>(*g, g->f32, p, (const cpx<float>*)d_phi, (cpx<float>*)d_hphi, Phi, nullptr);
+        launch_apply<float>(*g, (const cpx<float>*)d_phi, (cpx<float>*)d_hphi, Phi);
     }
     if (d_mu) {
-        hipError_t e = hipMemcpyAsync(d_mu, &g->st->mu, sizeof(double), hipMemcpyDeviceToDevice, g->stream);
-        if (e != hipSuccess) return hip_fail(g, e, "mu copy");
+        for (int b = 0; b < g->batch; ++b) {
+            hipError_t e = hipMemcpyAsync(d_mu + b, &g->st[b].mu, sizeof(double), hipMemcpyDeviceToDevice, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "mu copy");
+        }
     }
     return check_launch(g, "apply_H");
 }
@@ -506,28 +560,26 @@ int bec_apply_H(bec_grid g, const bec_params* pp, const void* d_phi, void* d_hph
 int bec_energy(bec_grid g, const bec_params* pp, const void* d_phi, bec_energies* out, int out_on_host) {
     int rc = check_grid(g);
     if (rc) return rc;
-    Params p;
-    if ((rc = validate_params(pp, p))) return rc;
     if (!d_phi || !out) return fail(BEC_EINVAL, "NULL pointer");
-    if (p.lam != 0.0 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
-    launch_set_params(*g, p);
+    if ((rc = upload_params(*g, pp))) return rc;
     if (g->precision == BEC_FP64)
-        launch_apply<double>(*g, g->f64, p, (const cpx<double>*)d_phi, g->f64.hphi, g->f64.Phi, nullptr);
+        launch_apply<double>(*g, (const cpx<double>*)d_phi, g->f64.hphi, g->f64.Phi);
     else
-        launch_apply<float>(*g, g->f32, p, (const cpx<float>*)d_phi, g->f32.hphi, g->f32.Phi, nullptr);
+        launch_apply<float>(*g, (const cpx<float>*)d_phi, g->f32.hphi, g->f32.Phi);
     if ((rc = check_launch(g, "energy"))) return rc;
-    DevState hs;
-    hipError_t e = hipMemcpyAsync(&hs, g->st, sizeof(DevState), hipMemcpyDeviceToHost, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return hip_fail(g, e, "energy readback");
-    bec_energies r;
-    r.E = hs.E; r.Ekin = hs.Ekin; r.Epot = hs.Epot; r.Eint = hs.Eint; r.Edip = hs.Edip; r.Erot = hs.Erot;
-    r.mu = hs.mu; r.mass = hs.mass;
-    r.virial = 2 * hs.Ekin - 2 * hs.Epot + 3 * hs.Eint + 3 * hs.Edip;
+    std::vector<DevState> hs;
+    if ((rc = read_states(*g, hs))) return rc;
+    std::vector<bec_energies> r(g->batch);
+    for (int b = 0; b < g->batch; ++b) {
+        const DevState& S = hs[b];
+        r[b].E = S.E; r[b].Ekin = S.Ekin; r[b].Epot = S.Epot; r[b].Eint = S.Eint; r[b].Edip = S.Edip;
+        r[b].Erot = S.Erot; r[b].mu = S.mu; r[b].mass = S.mass;
+        r[b].virial = 2 * S.Ekin - 2 * S.Epot + 3 * S.Eint + 3 * S.Edip;
+    }
     if (out_on_host) {
-        *out = r;
+        std::memcpy(out, r.data(), r.size() * sizeof(bec_energies));
     } else {
-        e = hipMemcpyAsync(out, &r, sizeof(r), hipMemcpyHostToDevice, g->stream);
+        hipError_t e = hipMemcpyAsync(out, r.data(), r.size() * sizeof(bec_energies), hipMemcpyHostToDevice, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "energy copy");
     }
@@ -539,6 +591,9 @@ int bec_fft3d(bec_grid g, const void* d_in, void* d_out, int dir) {
     if (rc) return rc;
     if (!d_in || !d_out) return fail(BEC_EINVAL, "NULL field pointer");
     if (dir != -1 && dir != 1) return fail(BEC_EINVAL, "dir must be -1 or +1");
+    // the transform needs no parameters; run with the solves marked active
+    hipError_t e = hipMemsetAsync(g->st, 0, g->batch * sizeof(DevState), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "fft3d state");
     if (g->precision == BEC_FP64)
         launch_fft3d<double>(*g, (const cpx<double>*)d_in, (cpx<double>*)d_out, dir);
     else
@@ -562,32 +617,33 @@ int bec_pcg_default_opts(bec_pcg_opts* o) {
     return BEC_OK;
 }
 
-int bec_pcg_solve(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_opts* opts, bec_pcg_result* res) {
+int bec_pcg_solve_batched(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_opts* opts,
+                          bec_pcg_result* res) {
     int rc = check_grid(g);
     if (rc) return rc;
-    Params p;
-    if ((rc = validate_params(pp, p))) return rc;
     if (!d_phi || !res) return fail(BEC_EINVAL, "NULL pointer");
     bec_pcg_opts o;
     if (opts) o = *opts; else bec_pcg_default_opts(&o);
     if (!(o.tol_res_inf >= 0.0) || o.max_iter < 0 || o.max_halvings < 0 || o.check_every < 1)
         return fail(BEC_EINVAL, "bad options");
-    if (p.lam != 0.0 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
-    return pcg_solve(*g, p, (cpx<double>*)d_phi, o, res);
+    if ((rc = upload_params(*g, pp))) return rc;
+    return pcg_solve(*g, (cpx<double>*)d_phi, o, res);
+}
+
+int bec_pcg_solve(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_opts* opts, bec_pcg_result* res) {
+    return bec_pcg_solve_batched(g, pp, d_phi, opts, res);
 }
 
 int bec_time_stage(bec_grid g, const bec_params* pp, const void* d_phi, int which, int reps, double* avg_ms) {
     int rc = check_grid(g);
     if (rc) return rc;
-    Params p;
-    if ((rc = validate_params(pp, p))) return rc;
     if (!d_phi || !avg_ms || reps < 1 || which < 0 || which > 6) return fail(BEC_EINVAL, "bad arguments");
     if (which != 3 && which != 4 && !g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
-    launch_set_params(*g, p);
+    if ((rc = upload_params(*g, pp))) return rc;
     if (g->precision == BEC_FP64)
-        *avg_ms = time_stage<double>(*g, g->f64, p, (const cpx<double>*)d_phi, which, reps);
+        *avg_ms = time_stage<double>(*g, (const cpx<double>*)d_phi, which, reps);
     else
-        *avg_ms = time_stage<float>(*g, g->f32, p, (const cpx<float>*)d_phi, which, reps);
+        *avg_ms = time_stage<float>(*g, (const cpx<float>*)d_phi, which, reps);
     return check_launch(g, "time_stage");
 }
 

@@ -27,6 +27,7 @@ constexpr int kThreads = 256;         // threads per block of every field kernel
 constexpr int kTileElems = 4096;      // complex elements held in LDS by one line-FFT block
 constexpr int kMaxStages = 12;
 constexpr int kMaxRed = 32;           // reduction slots per kernel
+constexpr int kRedBlocks = 1024;      // blocks of the grid-stride pointwise reductions
 
 // Per-size FFT plan (device-visible, passed by value).
 struct FftPlan {

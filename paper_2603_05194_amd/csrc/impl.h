@@ -7,11 +7,13 @@
 
 namespace bec {
 
+// physical parameters of one solve (validated copy of bec_params, dipole axis normalised)
 struct Params {
     double gamma[3], beta, lam, nd[3], omega;
 };
 
-// Device buffers of one precision, carved from the caller's workspace.
+// Device buffers of one precision, carved from the caller's workspace. Every field holds the
+// whole batch: solve b starts at b * (its per-solve size).
 template <typename R> struct Fields {
     cpx<R>* hphi = nullptr;   // H phi
     cpx<R>* acc = nullptr;    // line-operator accumulator
@@ -34,52 +36,53 @@ struct Grid {
     int n[3];
     double a[3], h[3], h3;
     int precision;            // 0: FP64 only; 1: FP64 + FP32 fields
+    int batch;                // number of same-grid solves held by the workspace
     hipStream_t stream;
     char* ws;
     size_t ws_bytes;
-    size_t ws_used;
     Fields<double> f64;
     Fields<float> f32;
-    double* uhat = nullptr;   // octant [Nx+1][Ny+1][Nz+1]
+    double* uhat = nullptr;   // octant [Nx+1][Ny+1][Nz+1], shared by the batch
     bool have_symbol = false;
-    DevState* st = nullptr;   // device scalar state
-    int* done_flag = nullptr; // points into st (done)
+    DevState* st = nullptr;   // device scalar state, one per solve
+    Params* dparams = nullptr;   // device copy of the per-solve parameters
+    int* dstop = nullptr;     // host-set stop flags, one per solve
     double* partials = nullptr;
-    size_t partials_cap = 0;
-    size_t partials_off = 0;
+    long part_stride = 0;     // doubles of partial sums per solve
     double* sym_scratch = nullptr;
     size_t sym_scratch_bytes = 0;
     int poisoned = 0;
     int use_rf = 1;           // power-of-two register-FFT fast paths (0: generic LDS kernels)
+    bool lam_any = false;     // some solve of the batch has lambda != 0
     // geometries
     Geo gz, gy, gx;           // N grid line passes (z: Nz, y: Ny, x: Nx)
-    Geo g_ay, g_ax, g_ax2, g_ayi;   // padded passes
-    int zf_L, zf2_L, zi_L;
-    hipGraphExec_t graph = nullptr;
-    int graph_prec = -1;
+    Geo g_ay, g_ax, g_ax2;    // padded passes (y forward/inverse, x, two-field x)
+    int zf_L;                 // packed lines per block of the runtime-length z pair kernels
+    Bat bt64, bt32;           // per-solve strides of the FP64 / FP32 buffers
 };
 
-// workspace layout
-size_t workspace_bytes(const int n[3], int precision);
-int carve(Grid& g);
+template <typename R> inline Fields<R>& fields(Grid& g);
+template <> inline Fields<double>& fields<double>(Grid& g) { return g.f64; }
+template <> inline Fields<float>& fields<float>(Grid& g) { return g.f32; }
+template <typename R> inline const Bat& bat(const Grid& g) { return sizeof(R) == 8 ? g.bt64 : g.bt32; }
 
-// launch wrappers (kernels.hip)
+// launch wrappers (kernels.hip). Parameters are read on the device from DevState[b].
 template <typename R> void launch_fft3d(Grid& g, const cpx<R>* in, cpx<R>* out, int dir);
-template <typename R> void launch_atkm(Grid& g, Fields<R>& f, const Params& p, const cpx<R>* phi, R* Phi, const int* done);
-template <typename R> void launch_apply(Grid& g, Fields<R>& f, const Params& p, const cpx<R>* phi, cpx<R>* hphi,
-                                        R* Phi, const int* done);
+template <typename R> void launch_atkm(Grid& g, const cpx<R>* phi, R* Phi);
+template <typename R> void launch_apply(Grid& g, const cpx<R>* phi, cpx<R>* hphi, R* Phi);
 void launch_symbol(Grid& g, std::vector<double>& tables_host_scratch);
-void launch_set_params(Grid& g, const Params& p);
+void launch_set_params(Grid& g);   // copies g.dparams[b] into st[b] (already uploaded)
 
 struct CtlOpts {
     double tol_res, tol_step, t_default, tau_ulps, dbg_t, dbg_c2;
     int max_iter, max_halv, dbg_flags, fp32;
 };
-template <typename R> void launch_pcg_iteration(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi, int parity);
-template <typename R> void launch_pcg_start(Grid& g, Fields<R>& f, const Params& p, cpx<R>* phi);
+template <typename R> void launch_pcg_iteration(Grid& g, cpx<R>* phi, int parity);
+template <typename R> void launch_pcg_start(Grid& g, cpx<R>* phi);
 void launch_ctl_init(Grid& g, const CtlOpts& o);
-void launch_ctl_phase(Grid& g, double tol, int max_iter);
-template <typename R> double time_stage(Grid& g, Fields<R>& f, const Params& p, const cpx<R>* phi, int which, int reps);
+void launch_ctl_phase(Grid& g, double tol, int max_iter, double tau_ulps, double eps_E);
+void launch_ctl_stop(Grid& g);
+template <typename R> double time_stage(Grid& g, const cpx<R>* phi, int which, int reps);
 void launch_to_f32(Grid& g, const cpx<double>* a, cpx<float>* b);
 void launch_to_f64_normalized(Grid& g, const cpx<float>* a, cpx<double>* b);
 

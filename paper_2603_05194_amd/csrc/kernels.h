@@ -30,19 +30,26 @@ struct DevState {
     double cPr, cPhi, cP;          // p <- cPr * Pr + cPhi * phi + cP * p
     double cRet, sRet;             // phi <- cRet * phi + sRet * p
     double t, c2, d1, beta_cg, pnorm;
-    double tau_E;
+    double tau_E, eps_E;
     // options
     double tol_res, tol_step, t_default, tau_ulps;
     double dbg_t, dbg_c2;
     int max_iter, max_halv, dbg_flags;
     // counters and flags
     int iter, halvings, resets, forced, restart, done, status, accepted_last;
-    int pad_;
+    int fp32_iters;
     // reduction landing area (filled by finalize kernels)
     double red[4][kMaxRed];
 };
 
 enum RedSlot { RS_APPLY = 0, RS_PREC = 1, RS_DIR = 2, RS_AUX = 3 };
+
+// Element strides between the solves of a batch (blockIdx.y selects the solve): complex N-grid
+// fields, real N-grid fields, the [Nx][Ny][Nz+1] and [Nx][2Ny][Nz+1] padded buffers, and the
+// per-solve partial-sum region.
+struct Bat {
+    long n, z, y, part;
+};
 
 template <typename R> struct Tables {
     FftPlan plan_z, plan_y, plan_x;          // N-grid lengths
