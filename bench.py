@@ -52,7 +52,8 @@ MEASURED_TRAFFIC = {
 def kernel_src_hash():
     import hashlib
     m = hashlib.sha256()
-    for f in ("regfft.h", "rfkern.inc", "fft.h", "common.h", "lines.h"):
+    for f in ("kernels.hip", "kernels.h", "ops.inc", "special.inc", "pcg.inc", "launch.inc", "regfft.h",
+              "fft.h", "common.h", "lines.h"):
         with open(os.path.join(ROOT, "paper_2603_05194_amd", "csrc", f), "rb") as fh:
             m.update(fh.read())
     return m.hexdigest()[:16]

@@ -90,6 +90,10 @@ def _lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_05194_amd.build`")
+        # torch ships its own HIP runtime under the same soname. Importing torch first makes the
+        # loader bind libbec.so to that copy; loading libbec.so first would pull in a second
+        # runtime that sees none of the memory or streams torch hands over.
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)

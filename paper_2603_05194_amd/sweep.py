@@ -1,0 +1,99 @@
+"""Batched parameter sweeps of ground states and the critical rotation frequency.
+
+A sweep of solves on several grid sizes runs as one batched solve per grid size (same box and
+grid within a batch: one launch per phase serves all of its solves). The critical rotation
+frequency for each dipolar strength is the first Omega at which the ground state carries a
+vortex, read as <L_z> = -E_rot / Omega >= 1/2 (Sec. 3, critical rotational frequency study).
+
+    python -m paper_2603_05194_amd.sweep [--quick] [--max-iter K] [--fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from collections import OrderedDict
+
+import numpy as np
+
+from . import BEC_FP32, BEC_FP64, BecGrid, bec_pcg_default_opts, make_params
+
+
+def group_by_grid(workloads):
+    groups = OrderedDict()
+    for i, w in enumerate(workloads):
+        groups.setdefault((tuple(w.n), tuple(w.a)), []).append(i)
+    return groups
+
+
+def run_sweep(workloads, guesses, precision=BEC_FP32, opts=None, log=None):
+    """Solve every workload (batched per grid). `guesses[i]` is a complex128 numpy array.
+    Returns one dict per workload with status, iterations, energies and <L_z>."""
+    import torch
+    opts = opts or bec_pcg_default_opts()
+    out = [None] * len(workloads)
+    for (n, a), idx in group_by_grid(workloads).items():
+        t0 = time.perf_counter()
+        g = BecGrid(n, a, precision=precision, batch=len(idx))
+        params = [make_params(workloads[i].gamma, workloads[i].beta, workloads[i].lam, workloads[i].ndip,
+                              workloads[i].omega) for i in idx]
+        phis = torch.from_numpy(np.stack([guesses[i] for i in idx])).to(g.device)
+        res = g.pcg_solve_batched(params, phis, opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for k, i in enumerate(idx):
+            r, w = res[k], workloads[i]
+            lz = -r.e.Erot / w.omega if w.omega != 0 else 0.0
+            out[i] = dict(name=w.name, n=list(n), omega=w.omega, lam=w.lam, beta=w.beta, status=r.status,
+                          iters=r.iters, fp32_iters=r.fp32_iters, res_inf=r.res_inf, E=r.e.E, mu=r.e.mu,
+                          Erot=r.e.Erot, Lz=lz, batch_seconds=dt)
+        if log:
+            log(f"grid {n}: {len(idx)} solves in {dt:.1f}s, iterations {min(res[k].iters for k in range(len(idx)))}"
+                f"..{max(res[k].iters for k in range(len(idx)))}, converged "
+                f"{sum(r.status == 0 for r in res)}/{len(idx)}")
+        del g
+    return out
+
+
+def critical_omega(results):
+    """Per dipolar strength: the first Omega (ascending) with <L_z> >= 1/2, and its bracket."""
+    by_lam = OrderedDict()
+    for r in results:
+        by_lam.setdefault(r["lam"], []).append(r)
+    out = OrderedDict()
+    for lam, rs in by_lam.items():
+        rs = sorted(rs, key=lambda r: r["omega"])
+        oc, lo = None, None
+        for i, r in enumerate(rs):
+            if r["Lz"] >= 0.5:
+                oc = r["omega"]
+                lo = rs[i - 1]["omega"] if i > 0 else 0.0
+                break
+        out[lam] = dict(omega_c=oc, bracket=[lo, oc], Lz=[round(r["Lz"], 6) for r in rs],
+                        omegas=[r["omega"] for r in rs])
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="quarter-size grids")
+    ap.add_argument("--fp64", action="store_true", help="FP64 only (default: FP32 bulk + FP64 polish)")
+    ap.add_argument("--max-iter", type=int, default=20000)
+    args = ap.parse_args(argv)
+    import bec_inputs as bi
+    ws = bi.batched_sweep(quick=args.quick)
+    guesses = [bi.initial_guess(w) for w in ws]
+    o = bec_pcg_default_opts()
+    o.max_iter = args.max_iter
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = run_sweep(ws, guesses, BEC_FP64 if args.fp64 else BEC_FP32, o, log)
+    total = time.perf_counter() - t0
+    oc = critical_omega(res)
+    print(json.dumps({"seconds": total, "solves": len(res), "converged": sum(r["status"] == 0 for r in res),
+                      "critical_omega": oc, "results": res}))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,23 @@
+"""Host logic of the batched sweep: grouping by grid and the critical-frequency rule."""
+import bec_inputs as bi
+from paper_2603_05194_amd.sweep import critical_omega, group_by_grid
+
+
+def test_sweep_workloads_and_groups():
+    ws = bi.batched_sweep()
+    assert len(ws) == 64
+    groups = group_by_grid(ws)
+    assert sorted(len(v) for v in groups.values()) == [16, 16, 16, 16]
+    assert sorted(k[0] for k in groups) == [(96, 96, 48), (128, 128, 48), (160, 160, 64), (192, 192, 64)]
+    lams = sorted({w.lam for w in ws})
+    assert lams == [100.0, 300.0, 500.0, 700.0]
+
+
+def test_critical_omega_rule():
+    rs = []
+    for lam, lz in ((1.0, [0.0, 0.01, 0.49, 0.98, 1.9]), (2.0, [0.0, 0.0, 0.0, 0.0, 0.2])):
+        for om, l in zip((0.1, 0.2, 0.3, 0.4, 0.5), lz):
+            rs.append(dict(lam=lam, omega=om, Lz=l))
+    oc = critical_omega(rs)
+    assert oc[1.0]["omega_c"] == 0.4 and oc[1.0]["bracket"] == [0.3, 0.4]
+    assert oc[2.0]["omega_c"] is None
