@@ -22,7 +22,7 @@ __all__ = [
     "Workload", "WORKLOADS", "grid_axes", "normalize", "gaussian_trap",
     "vortex", "guess_c", "guess_d", "guess_e", "guess_isotropic_a",
     "guess_thomas_fermi", "random_phase", "initial_guess", "batched_sweep",
-    "mlp_param_draw",
+    "mlp_param_draw", "mlp_init",
 ]
 
 
@@ -199,3 +199,17 @@ def mlp_param_draw(seed):
     th = rng.uniform(0.0, math.pi / 2.0)
     ph = rng.uniform(0.0, math.pi)
     return np.array([beta, ratio, omega, gz, th, ph])
+
+
+def mlp_init(dims, seed):
+    """Seeded initial weights of the d_in -> d_h -> d_h -> d_out network, packed
+    [W1 b1 W2 b2 W3 b3] as FP32: W uniform on +-sqrt(6/(fan_in + fan_out)) (Glorot and
+    Bengio's uniform scaling), biases zero."""
+    d_in, d_h, d_out = dims
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fo, fi in ((d_h, d_in), (d_h, d_h), (d_out, d_h)):
+        lim = math.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-lim, lim, fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)

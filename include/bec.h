@@ -155,6 +155,25 @@ int bec_pcg_default_opts(bec_pcg_opts* opts);
  * the transform of the Fourier coefficients (eq. "FourphiCo") used by the operators. */
 int bec_fft3d(bec_grid g, const void* d_in, void* d_out, int dir);
 
+/* Spectral (trigonometric) interpolation of `batch` fields from grid src to grid dst on the
+ * same box (Algorithm 2, step 2: hand-over of a ground state to another mesh; the paper leaves
+ * the interpolant open, this is the Fourier series of eq. "Fourphi" evaluated on the new
+ * points). Modes with |f_a| < min(N_src,a, N_dst,a)/2 are kept on every axis (both Nyquist
+ * modes dropped); refining zero-pads the spectrum, coarsening truncates it. d_in holds src
+ * fields in in_precision, d_out receives dst fields in out_precision (BEC_FP64: complex128,
+ * BEC_FP32: complex64). Batch sizes must match. Runs on src's stream (synchronising it when
+ * dst uses another stream); uses the FFT scratch and device state of both handles. */
+int bec_interp_spectral(bec_grid src, bec_grid dst, const void* d_in, int in_precision, void* d_out,
+                        int out_precision);
+/* Scales each complex128 field of the batch to unit mass h_x h_y h_z sum |phi|^2 = 1
+ * (the constraint of eq. "groundDef"). */
+int bec_normalize(bec_grid g, void* d_phi);
+/* Removes the global phase, which leaves the energy unchanged (Sec. 3, accuracy study):
+ * each complex128 field is multiplied by a unit complex number so that sum phi G is real and
+ * positive, G = exp(-(gamma_x x^2 + gamma_y y^2 + gamma_z z^2)/2) from p[b].gamma. A field with
+ * sum phi G = 0 is left unchanged. */
+int bec_gauge_fix(bec_grid g, const bec_params* p, void* d_phi);
+
 /* Measurement helper: runs one stage of the hot path `reps` times on the grid's stream and
  * returns the mean duration per run from HIP events (milliseconds). which = 0: the ATKM
  * padded x pass (forward, symbol multiply, inverse); 1: the whole ATKM potential of |phi|^2;

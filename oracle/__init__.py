@@ -12,7 +12,9 @@ Modules (each function cites the passage of the paper it follows):
   dipolar    dipolar potential via ATKM (Sec. 2.2, eqs. "DDI2Cou3D", "U_TrunFour")
   energy     discrete energy, H_phi, mu, inner product (Sec. 2.3)
   pcg        Riemannian PCG, Algorithm 1 (Sec. 2.3)
-  mlp        reference forward/backward of the initial-guess network (project addition)
+  interp     spectral interpolation between grids, unit mass, phase fix (Algorithm 2, Sec. 3)
+  mlp        forward pass, loss gradient and Adam step of the initial-guess network
+             (project addition; BF16 rounding emulated where the library rounds)
 
 Readings of the paper where it is silent or garbled are listed in each module's
 docstring where they apply. Every function here has a pin in tests/ that does not

@@ -49,11 +49,17 @@ class bec_pcg_result(C.Structure):
                 ("res_inf", C.c_double), ("step_inf", C.c_double), ("e", bec_energies)]
 
 
+class bec_mlp(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("d_h", C.c_int32), ("d_out", C.c_int32), ("params", C.c_void_p),
+                ("params_bf16", C.c_void_p), ("w2t_bf16", C.c_void_p), ("w3t_bf16", C.c_void_p),
+                ("grads", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p)]
+
+
 class BecError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
-        super().__init__(f"{where}: {code} ({_lib().bec_status_string(code).decode()}): "
-                         f"{_lib().bec_last_error().decode()}")
+        msg = (_lib().bec_mlp_last_error() if where.startswith(("bec_mlp", "bec_gemm")) else _lib().bec_last_error())
+        super().__init__(f"{where}: {code} ({_lib().bec_status_string(code).decode()}): {msg.decode()}")
 
 
 _LIB = None
@@ -81,6 +87,22 @@ _SIGS = {
     "bec_fft3d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "bec_time_stage": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.c_int,
                                  C.POINTER(C.c_double)]),
+    "bec_interp_spectral": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
+    "bec_normalize": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "bec_gauge_fix": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p]),
+    # learned initial guess (include/bec_mlp.h)
+    "bec_mlp_last_error": (C.c_char_p, []),
+    "bec_mlp_param_count": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
+    "bec_mlp_scratch_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
+    "bec_mlp_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "bec_mlp_forward": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                  C.c_void_p]),
+    "bec_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bec_mlp_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                    C.c_void_p]),
+    "bec_gemm_bf16_nt": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                   C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -198,6 +220,56 @@ def bec_time_stage(h, params, d_phi, which, reps) -> float:
     ms = C.c_double(0.0)
     _check(_lib().bec_time_stage(h, _params_arg(params), C.c_void_p(d_phi), which, reps, C.byref(ms)), "bec_time_stage")
     return ms.value
+
+
+def bec_interp_spectral(h_src, h_dst, d_in, in_precision, d_out, out_precision):
+    _check(_lib().bec_interp_spectral(h_src, h_dst, C.c_void_p(d_in), in_precision, C.c_void_p(d_out), out_precision),
+           "bec_interp_spectral")
+
+
+def bec_normalize(h, d_phi):
+    _check(_lib().bec_normalize(h, C.c_void_p(d_phi)), "bec_normalize")
+
+
+def bec_gauge_fix(h, params, d_phi):
+    _check(_lib().bec_gauge_fix(h, _params_arg(params), C.c_void_p(d_phi)), "bec_gauge_fix")
+
+
+def bec_mlp_param_count(d_in, d_h, d_out) -> int:
+    return int(_lib().bec_mlp_param_count(d_in, d_h, d_out))
+
+
+def bec_mlp_scratch_bytes(net: bec_mlp, batch) -> int:
+    out = C.c_size_t(0)
+    _check(_lib().bec_mlp_scratch_bytes(C.byref(net), batch, C.byref(out)), "bec_mlp_scratch_bytes")
+    return out.value
+
+
+def bec_mlp_sync(net, stream):
+    _check(_lib().bec_mlp_sync(C.byref(net), C.c_void_p(stream)), "bec_mlp_sync")
+
+
+def bec_mlp_forward(net, batch, d_x, d_idx, d_y, d_scratch, scratch_bytes, stream):
+    _check(_lib().bec_mlp_forward(C.byref(net), batch, C.c_void_p(d_x), C.c_void_p(d_idx) if d_idx else None,
+                                  C.c_void_p(d_y), C.c_void_p(d_scratch), scratch_bytes, C.c_void_p(stream)),
+           "bec_mlp_forward")
+
+
+def bec_mlp_loss_grad(net, batch, d_x, d_target, d_idx, d_y, d_loss, d_scratch, scratch_bytes, stream):
+    _check(_lib().bec_mlp_loss_grad(C.byref(net), batch, C.c_void_p(d_x), C.c_void_p(d_target),
+                                    C.c_void_p(d_idx) if d_idx else None, C.c_void_p(d_y) if d_y else None,
+                                    C.c_void_p(d_loss), C.c_void_p(d_scratch), scratch_bytes, C.c_void_p(stream)),
+           "bec_mlp_loss_grad")
+
+
+def bec_mlp_adam_step(net, lr, beta1, beta2, eps, t, stream):
+    _check(_lib().bec_mlp_adam_step(C.byref(net), lr, beta1, beta2, eps, t, C.c_void_p(stream)), "bec_mlp_adam_step")
+
+
+def bec_gemm_bf16_nt(M, N, K, d_A, lda, d_B, ldb, d_C, ldc, d_bias, splits, d_part, stream):
+    _check(_lib().bec_gemm_bf16_nt(M, N, K, C.c_void_p(d_A), lda, C.c_void_p(d_B), ldb, C.c_void_p(d_C), ldc,
+                                   C.c_void_p(d_bias) if d_bias else None, splits,
+                                   C.c_void_p(d_part) if d_part else None, C.c_void_p(stream)), "bec_gemm_bf16_nt")
 
 
 # ------------------------------------------------------------------ torch-facing helpers
@@ -328,6 +400,32 @@ class BecGrid:
         self.ensure_symbol()
         return bec_time_stage(self.handle, params, self._field(phi).data_ptr(), which, reps)
 
+    def interp_to(self, dst: "BecGrid", phis, out_precision=BEC_FP64):
+        """Spectral interpolation of `batch` fields on this grid to grid `dst` (same box).
+        phis: complex128 or complex64 tensor [batch, Nx, Ny, Nz] (or [Nx, Ny, Nz] for batch 1)."""
+        torch = self.torch
+        assert phis.is_contiguous() and phis.dtype in (torch.complex128, torch.complex64)
+        assert phis.numel() == self.batch * self.n[0] * self.n[1] * self.n[2]
+        in_prec = BEC_FP64 if phis.dtype == torch.complex128 else BEC_FP32
+        shape = ((self.batch,) if phis.dim() == 4 else ()) + dst.n
+        out = torch.empty(shape, dtype=torch.complex128 if out_precision == BEC_FP64 else torch.complex64,
+                          device=self.device)
+        bec_interp_spectral(self.handle, dst.handle, phis.data_ptr(), in_prec, out.data_ptr(), out_precision)
+        return out
+
+    def normalize_(self, phis):
+        assert phis.is_contiguous() and phis.dtype == self.torch.complex128
+        assert phis.numel() == self.batch * self.n[0] * self.n[1] * self.n[2]
+        bec_normalize(self.handle, phis.data_ptr())
+        return phis
+
+    def gauge_fix_(self, params_list, phis):
+        assert phis.is_contiguous() and phis.dtype == self.torch.complex128
+        assert phis.numel() == self.batch * self.n[0] * self.n[1] * self.n[2] and len(params_list) == self.batch
+        arr = (bec_params * self.batch)(*params_list)
+        bec_gauge_fix(self.handle, arr, phis.data_ptr())
+        return phis
+
     def pcg_solve(self, params, phi, opts=None):
         if params.lambda_ != 0.0:
             self.ensure_symbol()
@@ -344,3 +442,84 @@ class BecGrid:
         assert tuple(phis.shape) == (self.batch,) + self.n
         arr = (bec_params * self.batch)(*params_list)
         return bec_pcg_solve_batched(self.handle, arr, phis.data_ptr(), self.batch, opts)
+
+
+class Mlp:
+    """The learned-initial-guess network on torch-allocated buffers (include/bec_mlp.h).
+
+    `params` is the packed FP32 master vector [W1 b1 W2 b2 W3 b3]; set it with load_params."""
+
+    def __init__(self, d_in=6, d_h=512, d_out=32768, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.dims = (int(d_in), int(d_h), int(d_out))
+        P = bec_mlp_param_count(*self.dims)
+        self.P = P
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.params = torch.zeros(P, **f32)
+        self.grads = torch.zeros(P, **f32)
+        self.adam_m = torch.zeros(P, **f32)
+        self.adam_v = torch.zeros(P, **f32)
+        self.params_bf16 = torch.zeros(P, dtype=torch.int16, device=self.device)
+        self.w2t = torch.zeros(d_h * d_h, dtype=torch.int16, device=self.device)
+        self.w3t = torch.zeros(d_h * d_out, dtype=torch.int16, device=self.device)
+        self.net = bec_mlp(d_in, d_h, d_out, self.params.data_ptr(), self.params_bf16.data_ptr(), self.w2t.data_ptr(),
+                           self.w3t.data_ptr(), self.grads.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._scratch = None
+        self._scratch_batch = 0
+        self.step_count = 0
+
+    def offsets(self):
+        d_in, d_h, d_out = self.dims
+        o = {}
+        k = 0
+        for name, size in (("W1", d_h * d_in), ("b1", d_h), ("W2", d_h * d_h), ("b2", d_h), ("W3", d_out * d_h),
+                           ("b3", d_out)):
+            o[name] = (k, k + size)
+            k += size
+        return o
+
+    def load_params(self, flat):
+        """flat: FP32 host or device vector of length P (copied), then BF16 copies refreshed."""
+        t = self.torch.as_tensor(flat, dtype=self.torch.float32)
+        assert t.numel() == self.P
+        self.params.copy_(t.reshape(-1).to(self.device))
+        self.adam_m.zero_()
+        self.adam_v.zero_()
+        self.step_count = 0
+        bec_mlp_sync(self.net, self.stream.cuda_stream)
+
+    def scratch(self, batch):
+        if self._scratch is None or self._scratch_batch < batch:
+            nbytes = bec_mlp_scratch_bytes(self.net, batch)
+            self._scratch = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            self._scratch_batch = batch
+        return self._scratch
+
+    def forward(self, x, idx=None, batch=None):
+        torch = self.torch
+        batch = int(batch if batch is not None else (idx.numel() if idx is not None else x.shape[0]))
+        assert x.dtype == torch.float32 and x.is_contiguous()
+        y = torch.empty((batch, self.dims[2]), dtype=torch.float32, device=self.device)
+        sc = self.scratch(batch)
+        bec_mlp_forward(self.net, batch, x.data_ptr(), idx.data_ptr() if idx is not None else None, y.data_ptr(),
+                        sc.data_ptr(), sc.numel(), self.stream.cuda_stream)
+        return y
+
+    def loss_grad(self, x, target, idx=None, batch=None, want_y=False):
+        torch = self.torch
+        batch = int(batch if batch is not None else (idx.numel() if idx is not None else x.shape[0]))
+        assert x.dtype == torch.float32 and target.dtype == torch.float32
+        y = torch.empty((batch, self.dims[2]), dtype=torch.float32, device=self.device) if want_y else None
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        sc = self.scratch(batch)
+        bec_mlp_loss_grad(self.net, batch, x.data_ptr(), target.data_ptr(), idx.data_ptr() if idx is not None else None,
+                          y.data_ptr() if y is not None else None, loss.data_ptr(), sc.data_ptr(), sc.numel(),
+                          self.stream.cuda_stream)
+        return (loss, y) if want_y else loss
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        bec_mlp_adam_step(self.net, lr, beta1, beta2, eps, self.step_count, self.stream.cuda_stream)

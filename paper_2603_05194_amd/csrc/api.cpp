@@ -601,6 +601,59 @@ int bec_fft3d(bec_grid g, const void* d_in, void* d_out, int dir) {
     return check_launch(g, "fft3d");
 }
 
+int bec_interp_spectral(bec_grid src, bec_grid dst, const void* d_in, int in_precision, void* d_out,
+                        int out_precision) {
+    int rc = check_grid(src);
+    if (!rc) rc = check_grid(dst);
+    if (rc) return rc;
+    if (!d_in || !d_out) return fail(BEC_EINVAL, "NULL field pointer");
+    if ((in_precision != BEC_FP64 && in_precision != BEC_FP32) || (out_precision != BEC_FP64 && out_precision != BEC_FP32))
+        return fail(BEC_EINVAL, "precision must be BEC_FP64 or BEC_FP32");
+    if (src == dst) return fail(BEC_EINVAL, "src and dst must be different handles");
+    if (src->batch != dst->batch) return fail(BEC_EINVAL, "src and dst batch sizes differ");
+    for (int i = 0; i < 3; ++i)
+        if (!(std::fabs(src->a[i] - dst->a[i]) <= 1e-12 * std::fabs(dst->a[i])))
+            return fail(BEC_EINVAL, "src and dst boxes differ");
+    hipStream_t dst_stream = dst->stream;
+    dst->stream = src->stream;   // one stream orders the two grids' work
+    hipError_t e = hipMemsetAsync(src->st, 0, src->batch * sizeof(DevState), src->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(dst->st, 0, dst->batch * sizeof(DevState), src->stream);
+    if (e != hipSuccess) {
+        dst->stream = dst_stream;
+        return hip_fail(src, e, "interp state");
+    }
+    launch_interp(*src, *dst, d_in, in_precision == BEC_FP32, d_out, out_precision == BEC_FP32);
+    rc = check_launch(src, "interp");
+    if (!rc && dst_stream != src->stream) {
+        e = hipStreamSynchronize(src->stream);
+        if (e != hipSuccess) rc = hip_fail(src, e, "interp sync");
+    }
+    dst->stream = dst_stream;
+    return rc;
+}
+
+int bec_normalize(bec_grid g, void* d_phi) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_phi) return fail(BEC_EINVAL, "NULL field pointer");
+    launch_normalize(*g, (cpx<double>*)d_phi);
+    return check_launch(g, "normalize");
+}
+
+int bec_gauge_fix(bec_grid g, const bec_params* pp, void* d_phi) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_phi || !pp) return fail(BEC_EINVAL, "NULL pointer");
+    std::vector<Params> ps(g->batch);
+    for (int b = 0; b < g->batch; ++b)
+        if ((rc = validate_params(pp + b, ps[b]))) return rc;
+    hipError_t e = hipMemcpyAsync(g->dparams, ps.data(), ps.size() * sizeof(Params), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "params upload");
+    launch_gauge(*g, (cpx<double>*)d_phi);
+    return check_launch(g, "gauge fix");
+}
+
 int bec_pcg_default_opts(bec_pcg_opts* o) {
     if (!o) return fail(BEC_EINVAL, "NULL opts");
     std::memset(o, 0, sizeof(*o));

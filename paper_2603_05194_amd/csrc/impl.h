@@ -85,5 +85,9 @@ void launch_ctl_stop(Grid& g);
 template <typename R> double time_stage(Grid& g, const cpx<R>* phi, int which, int reps);
 void launch_to_f32(Grid& g, const cpx<double>* a, cpx<float>* b);
 void launch_to_f64_normalized(Grid& g, const cpx<float>* a, cpx<double>* b);
+// field utilities (gridops); `st` must be cleared (solves active) by the caller
+void launch_interp(Grid& src, Grid& dst, const void* in, int in_fp32, void* out, int out_fp32);
+void launch_normalize(Grid& g, cpx<double>* phi);
+void launch_gauge(Grid& g, cpx<double>* phi);
 
 }  // namespace bec

@@ -168,6 +168,7 @@ __global__ void k_sym_contract(const double* __restrict__ c, int ms, const doubl
 }
 
 #include "pcg.inc"
+#include "gridops.inc"
 
 }  // namespace bec
 

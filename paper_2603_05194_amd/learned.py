@@ -1,0 +1,254 @@
+"""Learned initial guess for Algorithm 1: training-set generation with the batched solver,
+training with the library's network kernels, and inference (network -> coarse field ->
+spectral interpolation -> unit mass).
+
+The network maps six problem parameters (beta, lambda/beta, Omega, gamma_z, theta_n, phi_n),
+gamma_x = gamma_y = 1, dipole axis n = (sin theta cos phi, sin theta sin phi, cos theta), to a
+complex 32 x 32 x 16 field on the box [-16,16]^2 x [-a_z, a_z]. The z half-width follows the
+trap: a_z = 2 sqrt(20 / g), evaluated at the lower edge g of the gamma_z band that holds the
+problem (bands 20 * 2^(k/3)), so that all problems of a band share one box and grid and can be
+solved in one batch. gamma_z = 20 gives a_z = 2.
+
+Targets are ground states computed by this library's own PCG on the 64 x 64 x 32 grid of the
+same box, phase-fixed (bec_gauge_fix) and truncated to the 32 x 32 x 16 Fourier modes
+(bec_interp_spectral). At inference the coarse output is interpolated to the target grid by
+the same spectral interpolation and normalised; Algorithm 1 then runs from it.
+
+    python -m paper_2603_05194_amd.learned --train 2000 --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import BEC_FP32, BEC_FP64, BecGrid, Mlp, bec_pcg_default_opts, make_params
+
+DIMS = (6, 512, 32768)
+COARSE = (32, 32, 16)
+TRAIN_N = (64, 64, 32)
+XY_HALF = 16.0
+GZ_RANGE = (4.0, 40.0)
+
+
+def gz_band(gz: float) -> int:
+    """Index k of the band [20 * 2^(k/3), 20 * 2^((k+1)/3)) holding gamma_z."""
+    return int(math.floor(3.0 * math.log2(gz / 20.0) + 1e-12))
+
+
+def box_for(gz: float):
+    lo = 20.0 * 2.0 ** (gz_band(gz) / 3.0)
+    return (XY_HALF, XY_HALF, 2.0 * math.sqrt(20.0 / lo))
+
+
+def features(draw) -> np.ndarray:
+    """Affine map of (beta, lambda/beta, Omega, gamma_z, theta, phi) from their sampling
+    ranges onto [-1, 1]."""
+    beta, ratio, om, gz, th, ph = (float(v) for v in draw)
+    return np.array([(beta - 1600.0) / 1400.0, (ratio - 0.4) / 0.4, (om - 0.475) / 0.475,
+                     (gz - 22.0) / 18.0, (th - math.pi / 4) / (math.pi / 4), (ph - math.pi / 2) / (math.pi / 2)],
+                    dtype=np.float32)
+
+
+def physical(draw):
+    beta, ratio, om, gz, th, ph = (float(v) for v in draw)
+    nd = (math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th))
+    return dict(gamma=(1.0, 1.0, gz), beta=beta, lam=ratio * beta, ndip=nd, omega=om)
+
+
+def params_of(draw):
+    p = physical(draw)
+    return make_params(p["gamma"], p["beta"], p["lam"], p["ndip"], p["omega"])
+
+
+def plain_guess(draw, n):
+    import bec_inputs as bi
+    p = physical(draw)
+    return bi.guess_d(tuple(n), box_for(p["gamma"][2]), p["gamma"], p["omega"])
+
+
+def by_band(draws):
+    groups = {}
+    for i, d in enumerate(draws):
+        groups.setdefault(gz_band(float(d[3])), []).append(i)
+    return groups
+
+
+def solve_batch(draws, n, guesses, precision, opts):
+    """Batched Algorithm 1 for draws of one band on grid n. Returns (fields [B, *n] tensor,
+    results, seconds)."""
+    import torch
+    a = box_for(float(draws[0][3]))
+    g = BecGrid(n, a, precision=precision, batch=len(draws))
+    phis = torch.from_numpy(np.ascontiguousarray(np.stack(guesses))).to(g.device)
+    t0 = time.perf_counter()
+    res = g.pcg_solve_batched([params_of(d) for d in draws], phis, opts)
+    torch.cuda.synchronize()
+    return g, phis, res, time.perf_counter() - t0
+
+
+def boundary_ratio(phis):
+    """max |phi| on the six boundary planes over max |phi|, per field (data check only)."""
+    m = phis.abs()
+    planes = [m[:, 0], m[:, -1], m[:, :, 0], m[:, :, -1], m[:, :, :, 0], m[:, :, :, -1]]
+    import torch
+    edge = torch.stack([p.flatten(1).amax(1) for p in planes]).amax(0)
+    return (edge / m.flatten(1).amax(1)).cpu().numpy()
+
+
+def generate(draws, max_iter=4000, batch=64, tol=1e-8, log=None):
+    """Training targets for `draws`: float32 [len, 32768] (complex64 32x32x16 interleaved),
+    per-draw status, and the boundary-ratio check."""
+    import torch
+    T = np.zeros((len(draws), DIMS[2]), dtype=np.float32)
+    info = [None] * len(draws)
+    opts = bec_pcg_default_opts()
+    opts.max_iter = int(max_iter)
+    opts.tol_res_inf = tol
+    for band, idx in sorted(by_band(draws).items()):
+        for s in range(0, len(idx), batch):
+            part = idx[s:s + batch]
+            ds = [draws[i] for i in part]
+            gs = [plain_guess(d, TRAIN_N) for d in ds]
+            g, phis, res, dt = solve_batch(ds, TRAIN_N, gs, BEC_FP32, opts)
+            br = boundary_ratio(phis)
+            g.gauge_fix_([params_of(d) for d in ds], phis)
+            gc = BecGrid(COARSE, g.a, batch=len(ds))
+            coarse = g.interp_to(gc, phis, out_precision=BEC_FP32)
+            torch.cuda.synchronize()
+            T[part] = coarse.reshape(len(ds), -1).view(torch.float32).cpu().numpy()
+            for k, i in enumerate(part):
+                r = res[k]
+                info[i] = dict(status=r.status, iters=r.iters, res=r.res_inf, E=r.e.E, boundary=float(br[k]))
+            if log:
+                its = [res[k].iters for k in range(len(ds))]
+                log(f"band {band} (a_z={g.a[2]:.3f}): {len(ds)} solves in {dt:.1f}s, iterations "
+                    f"{min(its)}..{max(its)}, converged {sum(r.status == 0 for r in res)}/{len(ds)}")
+            del g, gc, phis, coarse
+    return T, info
+
+
+def train(X, T, epochs=400, batch=128, lr=1e-3, seed=0, log=None, X_val=None, T_val=None):
+    """Adam on the mean squared error; step size decays by cosine to lr/20. Returns the
+    network and the per-epoch losses."""
+    import torch
+    import bec_inputs as bi
+    net = Mlp(*DIMS)
+    net.load_params(bi.mlp_init(DIMS, seed))
+    dX = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    dT = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32)).cuda()
+    n = X.shape[0]
+    rng = np.random.default_rng(seed + 1)
+    hist = []
+    steps = epochs * ((n + batch - 1) // batch)
+    k = 0
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = rng.permutation(n).astype(np.int32)
+        losses = []
+        for s in range(0, n, batch):
+            idx = torch.from_numpy(perm[s:s + batch]).cuda()
+            frac = k / max(1, steps - 1)
+            losses.append(net.loss_grad(dX, dT, idx=idx))
+            net.adam_step(lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * frac))))
+            k += 1
+        torch.cuda.synchronize()
+        ep_loss = float(torch.cat(losses).mean().item())
+        rec = dict(epoch=ep, loss=ep_loss)
+        if X_val is not None and (ep % 25 == 0 or ep == epochs - 1):
+            rec["val"] = evaluate_loss(net, X_val, T_val)
+        hist.append(rec)
+        if log and (ep % 25 == 0 or ep == epochs - 1):
+            log(f"epoch {ep}: loss {ep_loss:.4e}" + (f" val {rec['val']:.4e}" if "val" in rec else "")
+                + f" ({time.perf_counter() - t0:.1f}s)")
+    return net, hist
+
+
+def evaluate_loss(net, X, T):
+    """Mean squared error of the network on (X, T) by the loss kernel (overwrites net.grads)."""
+    import torch
+    dX = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    dT = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32)).cuda()
+    return float(net.loss_grad(dX, dT).item())
+
+
+def predict(net, draws, n):
+    """Initial guesses on grid n for draws of one gamma_z band: complex128 [B, *n], unit mass."""
+    import torch
+    a = box_for(float(draws[0][3]))
+    assert all(gz_band(float(d[3])) == gz_band(float(draws[0][3])) for d in draws)
+    X = torch.from_numpy(np.stack([features(d) for d in draws])).cuda()
+    y = net.forward(X)
+    coarse = y.view(torch.complex64).reshape((len(draws),) + COARSE).contiguous()
+    gc = BecGrid(COARSE, a, batch=len(draws))
+    gf = BecGrid(n, a, batch=len(draws))
+    fine = gc.interp_to(gf, coarse)
+    gf.normalize_(fine)
+    return fine
+
+
+def save(net, path, meta=None):
+    """BF16 weights (the values the kernels use) plus FP32 biases, as an .npz file."""
+    o = net.offsets()
+    pb = net.params_bf16.cpu().numpy().view(np.uint16)
+    p = net.params.cpu().numpy()
+    arrs = {}
+    for k, (a, b) in o.items():
+        arrs[k] = p[a:b] if k.startswith("b") else pb[a:b]
+    np.savez(path, dims=np.array(DIMS), meta=json.dumps(meta or {}), **arrs)
+
+
+def load(path):
+    """Network with the saved weights (BF16 weights widened to FP32 masters)."""
+    z = np.load(path, allow_pickle=False)
+    dims = tuple(int(v) for v in z["dims"])
+    net = Mlp(*dims)
+    parts = []
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        v = z[k]
+        if k.startswith("W"):
+            v = (v.astype(np.uint32) << 16).view(np.float32)
+        parts.append(v.astype(np.float32))
+    net.load_params(np.concatenate(parts))
+    return net
+
+
+def main(argv=None):
+    import bec_inputs as bi
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=2000, help="training draws (seeds 0..)")
+    ap.add_argument("--val", type=int, default=64, help="held-out draws (seeds 10^6..)")
+    ap.add_argument("--max-iter", type=int, default=4000)
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    draws = [bi.mlp_param_draw(s) for s in range(args.train)]
+    val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(args.val)]
+    T, info = generate(draws, args.max_iter, log=log)
+    Tv, infov = generate(val, args.max_iter, log=log)
+    t_gen = time.perf_counter() - t0
+    keep = [i for i, r in enumerate(info) if r["boundary"] <= 1e-6]
+    keepv = [i for i, r in enumerate(infov) if r["boundary"] <= 1e-6]
+    X = np.stack([features(draws[i]) for i in keep])
+    Xv = np.stack([features(val[i]) for i in keepv])
+    net, hist = train(X, T[keep], epochs=args.epochs, lr=args.lr, log=log, X_val=Xv, T_val=Tv[keepv])
+    summary = dict(train=len(draws), kept=len(keep), dropped_frac=1 - len(keep) / len(draws),
+                   val=len(val), val_kept=len(keepv), gen_seconds=t_gen,
+                   converged=sum(r["status"] == 0 for r in info),
+                   iters_median=float(np.median([r["iters"] for r in info])),
+                   final_loss=hist[-1]["loss"], final_val=hist[-1].get("val"),
+                   seconds=time.perf_counter() - t0)
+    if args.out:
+        save(net, args.out, summary)
+    print(json.dumps(dict(summary=summary, history=hist)))
+
+
+if __name__ == "__main__":
+    main()
