@@ -14,7 +14,11 @@ same box, phase-fixed (bec_gauge_fix) and truncated to the 32 x 32 x 16 Fourier 
 (bec_interp_spectral). At inference the coarse output is interpolated to the target grid by
 the same spectral interpolation and normalised; Algorithm 1 then runs from it.
 
-    python -m paper_2603_05194_amd.learned --train 2000 --out weights.npz
+    python -m paper_2603_05194_amd.learned --train 2000 --out weights.npz [--eval-grid 128 128 32]
+
+The shipped weights (data/mlp_weights.npz) were made with the defaults: 2000 training draws
+(seeds 0..1999) solved to ||r||_inf <= 1e-8 on 64 x 64 x 32, Adam with step 1e-3 decayed by
+cosine to 5e-5 over 1500 epochs of batch 64, initial weights from seed 0.
 """
 from __future__ import annotations
 
@@ -28,6 +32,9 @@ import numpy as np
 
 from . import BEC_FP32, BEC_FP64, BecGrid, Mlp, bec_pcg_default_opts, make_params
 
+import os
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "mlp_weights.npz")
 DIMS = (6, 512, 32768)
 COARSE = (32, 32, 16)
 TRAIN_N = (64, 64, 32)
@@ -132,7 +139,7 @@ def generate(draws, max_iter=4000, batch=64, tol=1e-8, log=None):
     return T, info
 
 
-def train(X, T, epochs=400, batch=128, lr=1e-3, seed=0, log=None, X_val=None, T_val=None):
+def train(X, T, epochs=1500, batch=64, lr=1e-3, seed=0, log=None, X_val=None, T_val=None):
     """Adam on the mean squared error; step size decays by cosine to lr/20. Returns the
     network and the per-epoch losses."""
     import torch
@@ -191,6 +198,55 @@ def predict(net, draws, n):
     return fine
 
 
+def evaluate(net, draws, n, precision=BEC_FP32, max_iter=200000, log=None):
+    """Algorithm 1 from the plain guess (phi_d of the trap Gaussian) and from the network's
+    guess, for every draw, batched per gamma_z band. Returns one record per draw with the
+    iterations, final energies and status of both runs, and the wall time of both batches."""
+    import torch
+    opts = bec_pcg_default_opts()
+    opts.max_iter = int(max_iter)
+    rows = [None] * len(draws)
+    for band, idx in sorted(by_band(draws).items()):
+        ds = [draws[i] for i in idx]
+        gs = [plain_guess(d, n) for d in ds]
+        g0, _, r0, t0 = solve_batch(ds, n, gs, precision, opts)
+        del g0
+        lg = predict(net, ds, n).cpu().numpy()
+        g1, _, r1, t1 = solve_batch(ds, n, list(lg), precision, opts)
+        del g1
+        for k, i in enumerate(idx):
+            rows[i] = dict(band=band, draw=[float(v) for v in draws[i]],
+                           plain=dict(status=r0[k].status, iters=r0[k].iters, E=r0[k].e.E, mu=r0[k].e.mu),
+                           learned=dict(status=r1[k].status, iters=r1[k].iters, E=r1[k].e.E, mu=r1[k].e.mu),
+                           plain_batch_s=t0, learned_batch_s=t1, batch=len(ds))
+        if log:
+            log(f"eval band {band}: {len(ds)} draws, plain {t0:.1f}s (iters median "
+                f"{np.median([r.iters for r in r0]):.0f}), learned {t1:.1f}s (iters median "
+                f"{np.median([r.iters for r in r1]):.0f})")
+        torch.cuda.synchronize()
+    return rows
+
+
+def summarize(rows, rel_tol=1e-10):
+    """Gain of the learned guess: median iteration ratio, batch-time ratio, and the count of
+    draws where it ends at a higher energy (a loss of the network) or a lower one."""
+    ok = [r for r in rows if r["plain"]["status"] == 0 and r["learned"]["status"] == 0]
+    ratio = [r["learned"]["iters"] / max(1, r["plain"]["iters"]) for r in ok]
+    worse = sum(r["learned"]["E"] > r["plain"]["E"] + rel_tol * abs(r["plain"]["E"]) for r in ok)
+    better = sum(r["learned"]["E"] < r["plain"]["E"] - rel_tol * abs(r["plain"]["E"]) for r in ok)
+    bands = {}
+    for r in rows:
+        bands.setdefault(r["band"], (r["plain_batch_s"], r["learned_batch_s"]))
+    tp = sum(v[0] for v in bands.values())
+    tl = sum(v[1] for v in bands.values())
+    return dict(draws=len(rows), both_converged=len(ok),
+                iters_plain_median=float(np.median([r["plain"]["iters"] for r in ok])) if ok else None,
+                iters_learned_median=float(np.median([r["learned"]["iters"] for r in ok])) if ok else None,
+                iter_ratio_median=float(np.median(ratio)) if ok else None,
+                learned_fewer_iters=sum(v < 1 for v in ratio), plain_seconds=tp, learned_seconds=tl,
+                time_ratio=tl / tp if tp > 0 else None, higher_energy=worse, lower_energy=better)
+
+
 def save(net, path, meta=None):
     """BF16 weights (the values the kernels use) plus FP32 biases, as an .npz file."""
     o = net.offsets()
@@ -200,6 +256,11 @@ def save(net, path, meta=None):
     for k, (a, b) in o.items():
         arrs[k] = p[a:b] if k.startswith("b") else pb[a:b]
     np.savez(path, dims=np.array(DIMS), meta=json.dumps(meta or {}), **arrs)
+
+
+def load_default():
+    """The shipped network (data/mlp_weights.npz)."""
+    return load(WEIGHTS)
 
 
 def load(path):
@@ -223,8 +284,12 @@ def main(argv=None):
     ap.add_argument("--train", type=int, default=2000, help="training draws (seeds 0..)")
     ap.add_argument("--val", type=int, default=64, help="held-out draws (seeds 10^6..)")
     ap.add_argument("--max-iter", type=int, default=4000)
-    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-grid", type=int, nargs=3, default=None,
+                    help="also solve the held-out draws from plain and learned guesses on this grid")
+    ap.add_argument("--drop", type=float, default=1e-2, help="drop draws with boundary |phi| above this x max")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)
@@ -234,20 +299,28 @@ def main(argv=None):
     T, info = generate(draws, args.max_iter, log=log)
     Tv, infov = generate(val, args.max_iter, log=log)
     t_gen = time.perf_counter() - t0
-    keep = [i for i, r in enumerate(info) if r["boundary"] <= 1e-6]
-    keepv = [i for i, r in enumerate(infov) if r["boundary"] <= 1e-6]
+    keep = [i for i, r in enumerate(info) if r["boundary"] <= args.drop]
+    keepv = [i for i, r in enumerate(infov) if r["boundary"] <= args.drop]
+    br = np.array([r["boundary"] for r in info])
+    log(f"boundary ratio quantiles (10/50/90/max): {np.quantile(br, [0.1, 0.5, 0.9, 1.0])}; kept {len(keep)}/{len(info)}")
     X = np.stack([features(draws[i]) for i in keep])
-    Xv = np.stack([features(val[i]) for i in keepv])
-    net, hist = train(X, T[keep], epochs=args.epochs, lr=args.lr, log=log, X_val=Xv, T_val=Tv[keepv])
+    Xv = np.stack([features(val[i]) for i in keepv]) if keepv else None
+    Tvk = Tv[keepv] if keepv else None
+    net, hist = train(X, T[keep], epochs=args.epochs, batch=args.batch, lr=args.lr, log=log, X_val=Xv, T_val=Tvk)
     summary = dict(train=len(draws), kept=len(keep), dropped_frac=1 - len(keep) / len(draws),
                    val=len(val), val_kept=len(keepv), gen_seconds=t_gen,
                    converged=sum(r["status"] == 0 for r in info),
+                   boundary_quantiles=[float(v) for v in np.quantile(br, [0.1, 0.5, 0.9, 1.0])],
                    iters_median=float(np.median([r["iters"] for r in info])),
                    final_loss=hist[-1]["loss"], final_val=hist[-1].get("val"),
                    seconds=time.perf_counter() - t0)
     if args.out:
         save(net, args.out, summary)
-    print(json.dumps(dict(summary=summary, history=hist)))
+    out = dict(summary=summary, history=hist)
+    if args.eval_grid:
+        rows = evaluate(net, [val[i] for i in keepv], tuple(args.eval_grid), log=log)
+        out["eval"] = dict(grid=args.eval_grid, summary=summarize(rows), rows=rows)
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
