@@ -2,9 +2,11 @@
 on one MI355X), with H phi throughput, PCG iteration rate, the dominant kernel's HBM roofline
 fraction, the mixed-precision path and the CPU oracle baseline on the host cores.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
-A step is one full solve (||H phi - mu phi||_inf <= 1e-8) from a seeded random-phase guess;
-inputs are resident in HBM before the timed region. Prints one JSON line.
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-learned] [--no-mg] [--quick]
+A step is one full FP64 solve (||H phi - mu phi||_inf <= 1e-8) from a seeded random-phase guess;
+inputs are resident in HBM before the timed region. The same line reports the same workload
+solved from the learned guess (FP32 bulk + FP64 polish; network and interpolation inside the
+timed region) and by the three-level cascadic multigrid of Algorithm 2. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -106,7 +108,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--with-mixed", action="store_true", help="also time mixed precision from the plain guess")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-mg", action="store_true")
     ap.add_argument("--quick", action="store_true", help="reduced grid (for testing the script)")
     ap.add_argument("--max-iter", type=int, default=None,
                     help="cap PCG iterations (profiling runs only; the result is then not a ground state)")
@@ -179,8 +183,50 @@ def main():
     achieved = kern[dom]["achieved_GBs"]
     log(f"apply {t_apply_ms:.3f} ms, atkm {t_atkm_ms:.3f} ms, copy {copy_gbs:.0f} GB/s, dominant {dom}")
 
+    # Algorithm 1 from the learned guess (network -> coarse field -> spectral interpolation),
+    # FP32 bulk + FP64 polish; the timed region includes the network and the interpolation.
+    ref = results[0]
+    learned = None
+    if not args.no_learned:
+        from paper_2603_05194_amd import learned as L
+        net = L.load_default()
+        draw = np.array([w.beta, w.lam / w.beta, w.omega, w.gamma[2], math.acos(w.ndip[2]),
+                         math.atan2(w.ndip[1], w.ndip[0])])
+        gm = bec.BecGrid(n, w.a, precision=bec.BEC_FP32)
+        gm.ensure_symbol()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phil = L.predict(net, [draw], n)[0].contiguous()
+        torch.cuda.synchronize()
+        t_net = time.perf_counter() - t0
+        rl = gm.pcg_solve(p, phil, opts)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        learned = {"s_to_ground_state": tl, "network_and_interp_s": t_net, "iters": rl.iters,
+                   "fp32_iters": rl.fp32_iters, "status": rl.status, "E": rl.e.E, "mu": rl.e.mu,
+                   "speedup_vs_fp64": s_per_solve / tl, "dE_vs_fp64": rl.e.E - ref.e.E,
+                   "dmu_vs_fp64": rl.e.mu - ref.e.mu}
+        log(f"mixed+learned: {tl:.3f}s iters {rl.iters} (fp32 {rl.fp32_iters}) dE {rl.e.E - ref.e.E:.2e}")
+        del gm, net
+
+    # Algorithm 2 (cascadic multigrid, three levels N/4 -> N/2 -> N), FP32 bulk + FP64 polish on
+    # each level, from the same random-phase guess generated on the coarsest grid.
+    mg = None
+    if not args.no_mg:
+        from paper_2603_05194_amd import multigrid as MG
+        nl0 = MG.levels(n)[0]
+        phi0 = torch.from_numpy(bi.initial_guess(bi.Workload(**{**w.to_dict(), "seed": 0}), nl0)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phim, recs = MG.solve(n, w.a, p, phi0, precision=bec.BEC_FP32, opts=opts)
+        torch.cuda.synchronize()
+        tmg = time.perf_counter() - t0
+        mg = {"s_to_ground_state": tmg, "levels": recs, "status": recs[-1]["status"], "E": recs[-1]["E"],
+              "speedup_vs_fp64": s_per_solve / tmg, "dE_vs_fp64": recs[-1]["E"] - ref.e.E}
+        log(f"multigrid: {tmg:.3f}s fine iters {recs[-1]['iters']} dE {recs[-1]['E'] - ref.e.E:.2e}")
+
     mixed = None
-    if not args.no_mixed:
+    if args.with_mixed:
         gm = bec.BecGrid(n, w.a, precision=bec.BEC_FP32)
         gm.ensure_symbol()
         phim = guess(0)
@@ -189,10 +235,8 @@ def main():
         rm = gm.pcg_solve(p, phim, opts)
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0
-        ref = results[0]
         mixed = {"s_to_ground_state": tm, "iters": rm.iters, "fp32_iters": rm.fp32_iters, "status": rm.status,
-                 "speedup_vs_fp64": (t_total / args.steps) / tm if args.steps else None,
-                 "dE_vs_fp64": rm.e.E - ref.e.E, "dmu_vs_fp64": rm.e.mu - ref.e.mu}
+                 "speedup_vs_fp64": s_per_solve / tm, "dE_vs_fp64": rm.e.E - ref.e.E, "dmu_vs_fp64": rm.e.mu - ref.e.mu}
         log(f"mixed: {tm:.3f}s iters {rm.iters} (fp32 {rm.fp32_iters}) dE {rm.e.E - ref.e.E:.2e}")
         del gm
 
@@ -230,7 +274,8 @@ def main():
         "atkm_per_s": 1e3 / t_atkm_ms,
         "symbol_precompute_s": t_symbol,
         "mixed": mixed,
-        "learned": None,
+        "learned": learned,
+        "multigrid": mg,
         "roofline": {"bound": "hbm", "kernel": kern[dom]["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (MEASURED_TRAFFIC[dom]["bytes"] if MEASURED_TRAFFIC.get(dom, {}).get("src") == kernel_src_hash()

@@ -30,8 +30,9 @@ def levels(n, count=3):
 def solve(n, a, params, guess, precision=BEC_FP64, opts=None, count=3, log=None, coarse_opts=None):
     """Algorithm 2 on grid n (box half-widths a) for one parameter set.
 
-    guess(nl) returns the complex128 numpy initial guess on the coarsest grid nl.
-    Returns (phi on grid n as a torch tensor, per-level records)."""
+    `guess` is the complex128 initial guess on the coarsest grid: a device tensor, or a
+    callable guess(nl) returning a numpy array. Returns (phi on grid n as a torch tensor,
+    per-level records)."""
     import torch
     opts = opts or bec_pcg_default_opts()
     coarse_opts = coarse_opts or opts
@@ -42,7 +43,8 @@ def solve(n, a, params, guess, precision=BEC_FP64, opts=None, count=3, log=None,
     for li, nl in enumerate(grids):
         g = BecGrid(nl, a, precision=precision)
         if prev is None:
-            phi = torch.from_numpy(np.ascontiguousarray(guess(nl))).to(g.device)
+            phi = guess if torch.is_tensor(guess) else torch.from_numpy(np.ascontiguousarray(guess(nl))).to(g.device)
+            assert tuple(phi.shape) == tuple(nl)
         else:
             phi = prev.interp_to(g, phi)
             g.normalize_(phi)
