@@ -133,7 +133,9 @@ Layout layout(const int n[3], int precision, int batch) {
     maxt = std::max(maxt, (size_t)n[0] * (n[2] + 1));              // y passes
     maxt = std::max(maxt, (size_t)n[0] * n[1]);                    // z passes
     maxt = std::max(maxt, (size_t)kRedBlocks);
-    L.part_stride = (long)(maxt * 12 + 64);
+    // room for the partial rows of every reduction finished by one k_fin launch (<= 18 slots
+    // of at most maxt rows each, rounded per segment)
+    L.part_stride = (long)(maxt * 24 + 64);
     const int ms = 651;
     size_t sd = 2 * ms;
     for (int d = 0; d < 3; ++d) sd += (size_t)ms * (n[d] + 1) + 2 * ((size_t)std::ceil(M_PI * n[d] / 2.0) + 80);

@@ -44,6 +44,21 @@ struct DevState {
 
 enum RedSlot { RS_APPLY = 0, RS_PREC = 1, RS_DIR = 2, RS_AUX = 3 };
 
+// Partial-sum segments finished by one k_fin launch (offsets in doubles within a solve's region)
+constexpr int kFinQ = 10;     // slots per segment at most
+constexpr int kFinSeg = 6;    // segments per launch at most
+struct FinSeg {
+    long off;
+    int nb, nq;
+    unsigned maxmask;
+    int row, q0;
+};
+struct FinList {
+    int n;
+    FinSeg s[kFinSeg];
+};
+enum FinCtl { FC_NONE = 0, FC_RES = 1, FC_DIR = 2, FC_STEP = 3, FC_POST = 4, FC_APPLY = 5 };
+
 // Element strides between the solves of a batch (blockIdx.y selects the solve): complex N-grid
 // fields, real N-grid fields, the [Nx][Ny][Nz+1] and [Nx][2Ny][Nz+1] padded buffers, and the
 // per-solve partial-sum region.

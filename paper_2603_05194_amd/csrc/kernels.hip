@@ -101,10 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict_
 
 // Energy parts from the apply reductions (row RS_APPLY):
 //   [0..1] z (kin, rot), [2..3] y (kin, rot), [4..10] x (kin, rot, V rho, rho^2, Phi rho, rho, mu)
-__global__ void k_apply_finish(DevState* st, int nbatch) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbatch) return;
-    DevState& S = st[b];
+__device__ void apply_finish(DevState& S) {
     if (S.done) return;
     const double* r = S.red[RS_APPLY];
     const double h3 = S.h3;
@@ -116,6 +113,12 @@ __global__ void k_apply_finish(DevState* st, int nbatch) {
     S.mass = h3 * r[9];
     S.mu = h3 * r[10];
     S.E = S.Ekin + S.Epot + S.Eint + S.Edip + S.Erot;
+}
+
+__global__ void k_apply_finish(DevState* st, int nbatch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbatch) return;
+    apply_finish(st[b]);
 }
 
 // ------------------------------------------------------------------ symbol
@@ -168,6 +171,75 @@ __global__ void k_sym_contract(const double* __restrict__ c, int ms, const doubl
 }
 
 #include "pcg.inc"
+
+// ------------------------------------------------------------------ fused finalize + control
+// One block per solve. Each segment holds nb per-block partial rows of nq slots at offset `off`
+// of the solve's partial region; every thread sums its rows in order, waves reduce by shuffles,
+// the four wave results are combined in a fixed order into st[b].red[row][q0 + q]. Then one
+// thread runs the control step that consumes the sums (CTL), replacing separate finalize and
+// control launches.
+template <int CTL>
+__global__ __launch_bounds__(kThreads) void k_fin(const double* __restrict__ partials, long part_stride, FinList L,
+                                                  DevState* __restrict__ st) {
+    const int b = blockIdx.x;
+    if (st[b].done) return;
+    __shared__ double sh[kThreads / 64][kFinQ];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int si = 0; si < L.n; ++si) {
+        const FinSeg sg = L.s[si];
+        const double* p = partials + b * part_stride + sg.off;
+        double acc[kFinQ];
+#pragma unroll
+        for (int q = 0; q < kFinQ; ++q) acc[q] = 0.0;
+        // four rows per thread per round, all loads issued before any is used
+        constexpr int U = 4;
+        for (int i0 = threadIdx.x; i0 < sg.nb; i0 += U * kThreads) {
+            double y[U][kFinQ];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kThreads;
+#pragma unroll
+                for (int q = 0; q < kFinQ; ++q) y[u][q] = (q < sg.nq && i < sg.nb) ? p[(long)i * sg.nq + q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int q = 0; q < kFinQ; ++q)
+                    if (q < sg.nq) acc[q] = ((sg.maxmask >> q) & 1u) ? fmax(acc[q], y[u][q]) : acc[q] + y[u][q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kFinQ; ++q) {
+            if (q < sg.nq) {
+                const bool mx = (sg.maxmask >> q) & 1u;
+                double x = acc[q];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double y = __shfl_xor(x, off, 64);
+                    x = mx ? fmax(x, y) : x + y;
+                }
+                if (lane == 0) sh[wave][q] = x;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < sg.nq) {
+            const int q = threadIdx.x;
+            const bool mx = (sg.maxmask >> q) & 1u;
+            double x = sh[0][q];
+            for (int w = 1; w < kThreads / 64; ++w) x = mx ? fmax(x, sh[w][q]) : x + sh[w][q];
+            st[b].red[sg.row][sg.q0 + q] = x;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        DevState& S = st[b];
+        if constexpr (CTL == FC_RES) ctl_res(S);
+        else if constexpr (CTL == FC_DIR) ctl_dir(S);
+        else if constexpr (CTL == FC_STEP) ctl_step(S);
+        else if constexpr (CTL == FC_POST) ctl_post(S);
+        else if constexpr (CTL == FC_APPLY) apply_finish(S);
+    }
+}
 #include "gridops.inc"
 
 }  // namespace bec
