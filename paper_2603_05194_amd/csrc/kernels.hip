@@ -41,6 +41,42 @@ __device__ __forceinline__ double sym_prime(const SymArgs& s, const double* nd, 
     return (3.0 * nn * u - 1.0) * s.scale;
 }
 
+// S'_k along one padded x line (fixed ky, kz), with the line constants hoisted:
+//   (n.nu)^2 = a sx^2 + b sx + c  (b = 0 on the kx Nyquist plane), sx the signed kx index,
+// and the octant row U[.][|sy|][kz] read with stride (Ny+1)(Nz+1). Equal to sym_prime up to
+// rounding order.
+struct SymLine {
+    const double* row;
+    long stride;
+    double a, b, c, scale;
+    int nx;
+};
+
+__device__ __forceinline__ SymLine sym_line(const SymArgs& s, const double* nd, int ky, int kz) {
+    const int sy = ky < s.ny ? ky : ky - 2 * s.ny;
+    const int sz = kz < s.nz ? kz : -s.nz;
+    const bool qy = ky == s.ny, qz = kz == s.nz;
+    const double vy = sy * s.py, vz = sz * s.pz;
+    SymLine L;
+    L.a = nd[0] * nd[0] * s.px * s.px;
+    L.b = 2.0 * nd[0] * s.px * ((qy ? 0.0 : nd[1] * vy) + (qz ? 0.0 : nd[2] * vz));
+    L.c = nd[1] * nd[1] * vy * vy + nd[2] * nd[2] * vz * vz + ((qy || qz) ? 0.0 : 2.0 * nd[1] * nd[2] * vy * vz);
+    const int ay = sy < 0 ? -sy : sy;
+    L.stride = (long)(s.ny + 1) * (s.nz + 1);
+    L.row = s.uhat + (long)ay * (s.nz + 1) + kz;
+    L.scale = s.scale;
+    L.nx = s.nx;
+    return L;
+}
+
+__device__ __forceinline__ double sym_eval(const SymLine& L, int kx) {
+    const int sx = kx < L.nx ? kx : kx - 2 * L.nx;
+    const double v = (double)sx;
+    const double nn = (L.a * v + (kx == L.nx ? 0.0 : L.b)) * v + L.c;
+    const double u = L.row[(long)(sx < 0 ? -sx : sx) * L.stride];
+    return (3.0 * nn * u - 1.0) * L.scale;
+}
+
 __device__ __forceinline__ int fft_signed(int k, int n) { return k < n / 2 ? k : k - n; }
 
 template <typename R> __device__ __forceinline__ R rho_of(cpx<R> a) { return a.x * a.x + a.y * a.y; }
