@@ -255,7 +255,7 @@ def save(net, path, meta=None):
     arrs = {}
     for k, (a, b) in o.items():
         arrs[k] = p[a:b] if k.startswith("b") else pb[a:b]
-    np.savez(path, dims=np.array(DIMS), meta=json.dumps(meta or {}), **arrs)
+    np.savez(path, dims=np.array(net.dims), meta=json.dumps(meta or {}), **arrs)
 
 
 def load_default():
