@@ -119,6 +119,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    # the library prints a progress line to stderr every 30 s of a long solve
+    os.environ.setdefault("BEC_PROGRESS", "30")
     import numpy as np
     import torch
     import bec_inputs as bi
