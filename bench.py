@@ -45,9 +45,9 @@ def pass_bytes(which, n, csize):
 # calibration; see the hbm_traffic summary under profiles/), valid while the kernel sources
 # hash to `src`.
 MEASURED_TRAFFIC = {
-    "y_fwd": {"bytes": 214.0e6, "src": "1483827c41771126"},
-    "x_pass": {"bytes": 416.5e6, "src": "1483827c41771126"},
-    "x_pars2": {"bytes": 382.7e6, "src": "1483827c41771126"},
+    "y_fwd": {"bytes": 280.9e6, "src": "c036e936025eb207"},
+    "x_pass": {"bytes": 465.8e6, "src": "c036e936025eb207"},
+    "x_pars2": {"bytes": 465.7e6, "src": "c036e936025eb207"},
 }
 
 
