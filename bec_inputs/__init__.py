@@ -22,7 +22,7 @@ __all__ = [
     "Workload", "WORKLOADS", "grid_axes", "normalize", "gaussian_trap",
     "vortex", "guess_c", "guess_d", "guess_e", "guess_isotropic_a",
     "guess_thomas_fermi", "random_phase", "initial_guess", "batched_sweep",
-    "mlp_param_draw", "mlp_init",
+    "mlp_param_draw", "mlp_init", "paper_guesses", "PAPER_GUESS_NAMES",
 ]
 
 
@@ -213,3 +213,22 @@ def mlp_init(dims, seed):
         parts.append(rng.uniform(-lim, lim, fo * fi))
         parts.append(np.zeros(fo))
     return np.concatenate(parts).astype(np.float32)
+
+
+PAPER_GUESS_NAMES = ("a", "b", "b_bar", "c", "c_bar", "d", "d_bar", "e", "e_bar", "f")
+
+
+def paper_guesses(n, a, gamma, beta, omega):
+    """The ten starting states listed in Sec. 3, in order (a), (b), conj(b), (c), conj(c), (d),
+    conj(d), (e), conj(e), (f): phi_a is the isotropic Gaussian pi^(-3/4) exp(-|x|^2/2),
+    phi_b = N[(x + i y) phi_a], (c) = N[phi_a + phi_b], (d) = N[(1-Omega) phi_a + Omega phi_b],
+    (e) = N[Omega phi_a + (1-Omega) phi_b], (f) the normalised Thomas-Fermi profile; N[.]
+    normalises on the grid. Returns a complex128 array [10][Nx][Ny][Nz]."""
+    n = tuple(n)
+    pa = normalize(guess_isotropic_a(n, a), n, a)
+    pb = vortex(n, a, pa)
+    pc = normalize(pa + pb, n, a)
+    pd = normalize((1.0 - omega) * pa + omega * pb, n, a)
+    pe = normalize(omega * pa + (1.0 - omega) * pb, n, a)
+    pf = guess_thomas_fermi(n, a, gamma, beta)
+    return np.stack([pa, pb, np.conj(pb), pc, np.conj(pc), pd, np.conj(pd), pe, np.conj(pe), pf])

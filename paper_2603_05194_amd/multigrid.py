@@ -28,12 +28,17 @@ def levels(n, count=3):
 
 
 def solve(n, a, params, guess, precision=BEC_FP64, opts=None, count=3, log=None, coarse_opts=None):
-    """Algorithm 2 on grid n (box half-widths a) for one parameter set.
+    """Algorithm 2 on grid n (box half-widths a).
 
-    `guess` is the complex128 initial guess on the coarsest grid: a device tensor, or a
-    callable guess(nl) returning a numpy array. Returns (phi on grid n as a torch tensor,
-    per-level records)."""
+    `params` is one bec_params, or a list of them to run a batch of solves through the cascade
+    together (one launch per phase on every level). `guess` is the complex128 initial guess on
+    the coarsest grid ([Nx][Ny][Nz], or [batch][Nx][Ny][Nz] for a list of params): a device
+    tensor, a numpy array, or a callable guess(nl) returning a numpy array. Returns (phi on grid n as a torch
+    tensor, per-level records: one dict per level, or one list of dicts per level for a batch)."""
     import torch
+    batched = isinstance(params, (list, tuple))
+    plist = list(params) if batched else [params]
+    B = len(plist)
     opts = opts or bec_pcg_default_opts()
     coarse_opts = coarse_opts or opts
     grids = levels(n, count)
@@ -41,21 +46,27 @@ def solve(n, a, params, guess, precision=BEC_FP64, opts=None, count=3, log=None,
     phi = None
     prev = None
     for li, nl in enumerate(grids):
-        g = BecGrid(nl, a, precision=precision)
+        g = BecGrid(nl, a, precision=precision, batch=B)
         if prev is None:
-            phi = guess if torch.is_tensor(guess) else torch.from_numpy(np.ascontiguousarray(guess(nl))).to(g.device)
-            assert tuple(phi.shape) == tuple(nl)
+            if torch.is_tensor(guess):
+                phi = guess
+            else:
+                arr = guess if isinstance(guess, np.ndarray) else guess(nl)
+                phi = torch.from_numpy(np.ascontiguousarray(arr)).to(g.device)
+            phi = phi.reshape((B,) + tuple(nl)).contiguous()
         else:
             phi = prev.interp_to(g, phi)
             g.normalize_(phi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = g.pcg_solve(params, phi, opts if li == len(grids) - 1 else coarse_opts)
+        res = g.pcg_solve_batched(plist, phi, opts if li == len(grids) - 1 else coarse_opts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        recs.append(dict(grid=list(nl), status=r.status, iters=r.iters, fp32_iters=r.fp32_iters, res=r.res_inf,
-                         E=r.e.E, mu=r.e.mu, seconds=dt))
+        lv = [dict(grid=list(nl), status=r.status, iters=r.iters, fp32_iters=r.fp32_iters, res=r.res_inf, E=r.e.E,
+                   mu=r.e.mu, virial=r.e.virial, seconds=dt) for r in res]
+        recs.append(lv if batched else lv[0])
         if log:
-            log(f"level {li} {nl}: {r.iters} iterations, {dt:.2f}s, E {r.e.E:.12f}, res {r.res_inf:.2e}")
+            log(f"level {li} {nl}: iterations {min(r.iters for r in res)}..{max(r.iters for r in res)}, {dt:.2f}s, "
+                f"E min {min(r.e.E for r in res):.12f}")
         prev = g
-    return phi, recs
+    return (phi if batched else phi[0]), recs
