@@ -56,3 +56,24 @@ def test_mlp_init_is_seeded_and_glorot_scaled():
     W1 = a[:96]
     assert np.max(np.abs(W1)) <= math.sqrt(6.0 / 22.0)
     assert not np.any(a[96:112])   # b1 = 0
+
+
+def test_paper_guesses_follow_the_listed_combinations():
+    import bec_inputs as bi
+    n, a = (12, 10, 8), (4.0, 5.0, 6.0)
+    g = bi.paper_guesses(n, a, (1.0, 2.0, 0.5), 300.0, 0.3)
+    assert g.shape == (10,) + n
+    h3 = np.prod([2 * a[i] / n[i] for i in range(3)])
+    for k in range(10):
+        assert h3 * np.sum(np.abs(g[k]) ** 2) == pytest.approx(1.0, abs=1e-13)
+    names = dict(zip(bi.PAPER_GUESS_NAMES, g))
+    X, Y, Z = np.meshgrid(*[-a[i] + np.arange(n[i]) * 2 * a[i] / n[i] for i in range(3)], indexing="ij")
+    ga = np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / 2)
+    assert np.allclose(names["a"], ga / np.sqrt(h3 * np.sum(ga ** 2)), rtol=1e-13, atol=0)
+    vb = (X + 1j * Y) * ga
+    assert np.allclose(names["b"], vb / np.sqrt(h3 * np.sum(np.abs(vb) ** 2)), rtol=1e-12, atol=1e-15)
+    for k in ("b", "c", "d", "e"):
+        assert np.array_equal(names[k + "_bar"], np.conj(names[k]))
+    mix = 0.7 * names["a"] + 0.3 * names["b"]
+    assert np.allclose(names["d"], mix / np.sqrt(h3 * np.sum(np.abs(mix) ** 2)), rtol=1e-12, atol=1e-15)
+    assert np.all(names["f"].imag == 0) and np.all(names["f"].real >= 0)
