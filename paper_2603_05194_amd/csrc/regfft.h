@@ -63,13 +63,22 @@ __device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line
     for (int b = 0; b < BPT; ++b) {
         const int j = jb + TPL * b;
         if constexpr (Ns > 1) {
+            // one table read per butterfly; the other twiddles are its powers (at most three
+            // products deep: w2 = w1 w1, w3 = w2 w1, w4 = w2 w2, w5 = w4 w1, w6 = w3 w3, w7 = w4 w3)
             const int jm = j & (Ns - 1);
-#pragma unroll
-            for (int k = 1; k < RD; ++k) {
-                cpx<R> w = tw[jm * k * (N / (Ns * RD))];
-                if constexpr (DIR > 0) w = conj(w);
-                v[b * RD + k] = cmul(v[b * RD + k], w);
+            cpx<R> w[RD];
+            w[1] = tw[jm * (N / (Ns * RD))];
+            if constexpr (DIR > 0) w[1] = conj(w[1]);
+            if constexpr (RD > 2) w[2] = cmul(w[1], w[1]);
+            if constexpr (RD > 3) w[3] = cmul(w[2], w[1]);
+            if constexpr (RD > 4) {
+                w[4] = cmul(w[2], w[2]);
+                w[5] = cmul(w[4], w[1]);
+                w[6] = cmul(w[3], w[3]);
+                w[7] = cmul(w[4], w[3]);
             }
+#pragma unroll
+            for (int k = 1; k < RD; ++k) v[b * RD + k] = cmul(v[b * RD + k], w[k]);
         }
         dft_small<RD, DIR>(&v[b * RD]);
     }
