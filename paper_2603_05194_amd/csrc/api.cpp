@@ -517,9 +517,8 @@ int bec_atkm_symbol(bec_grid g, double* d_out) {
     if ((rc = check_launch(g, "symbol"))) return rc;
     g->have_symbol = true;
     if (d_out) {
-        const size_t bytes = (size_t)(g->n[0] + 1) * (g->n[1] + 1) * (g->n[2] + 1) * sizeof(double);
-        hipError_t e = hipMemcpyAsync(d_out, g->uhat, bytes, hipMemcpyDeviceToDevice, g->stream);
-        if (e != hipSuccess) return hip_fail(g, e, "symbol copy");
+        launch_symbol_out(*g, d_out);
+        if ((rc = check_launch(g, "symbol copy"))) return rc;
     }
     return BEC_OK;
 }

@@ -42,7 +42,7 @@ struct Grid {
     size_t ws_bytes;
     Fields<double> f64;
     Fields<float> f32;
-    double* uhat = nullptr;   // octant [Nx+1][Ny+1][Nz+1], shared by the batch
+    double* uhat = nullptr;   // symbol octant in the working layout [Ny+1][Nz+1][Nx+1], shared by the batch
     bool have_symbol = false;
     DevState* st = nullptr;   // device scalar state, one per solve
     Params* dparams = nullptr;   // device copy of the per-solve parameters
@@ -71,6 +71,7 @@ template <typename R> void launch_fft3d(Grid& g, const cpx<R>* in, cpx<R>* out, 
 template <typename R> void launch_atkm(Grid& g, const cpx<R>* phi, R* Phi);
 template <typename R> void launch_apply(Grid& g, const cpx<R>* phi, cpx<R>* hphi, R* Phi);
 void launch_symbol(Grid& g, std::vector<double>& tables_host_scratch);
+void launch_symbol_out(Grid& g, double* out);   // octant layout [Nx+1][Ny+1][Nz+1]
 void launch_set_params(Grid& g);   // copies g.dparams[b] into st[b] (already uploaded)
 
 struct CtlOpts {

@@ -18,7 +18,7 @@ namespace bec {
 
 // ------------------------------------------------------------------ geometry helpers
 struct SymArgs {
-    const double* uhat;   // octant [nx+1][ny+1][nz+1]
+    const double* uhat;   // octant values in the working layout [ny+1][nz+1][nx+1]
     int nx, ny, nz;       // N grid (padded axes have 2N points)
     double px, py, pz;    // pi / (2 a): padded frequency step
     double scale;         // 1 / (8 N)
@@ -37,17 +37,15 @@ __device__ __forceinline__ double sym_prime(const SymArgs& s, const double* nd, 
     if (!(qx || qz)) nn += 2.0 * nd[0] * nd[2] * vx * vz;
     if (!(qy || qz)) nn += 2.0 * nd[1] * nd[2] * vy * vz;
     const int ax = sx < 0 ? -sx : sx, ay = sy < 0 ? -sy : sy;
-    const double u = s.uhat[((long)ax * (s.ny + 1) + ay) * (s.nz + 1) + kz];
+    const double u = s.uhat[((long)ay * (s.nz + 1) + kz) * (s.nx + 1) + ax];
     return (3.0 * nn * u - 1.0) * s.scale;
 }
 
 // S'_k along one padded x line (fixed ky, kz), with the line constants hoisted:
 //   (n.nu)^2 = a sx^2 + b sx + c  (b = 0 on the kx Nyquist plane), sx the signed kx index,
-// and the octant row U[.][|sy|][kz] read with stride (Ny+1)(Nz+1). Equal to sym_prime up to
-// rounding order.
+// and the contiguous symbol row U[|sy|][kz][.]. Equal to sym_prime up to rounding order.
 struct SymLine {
     const double* row;
-    long stride;
     double a, b, c, scale;
     int nx;
 };
@@ -62,8 +60,7 @@ __device__ __forceinline__ SymLine sym_line(const SymArgs& s, const double* nd, 
     L.b = 2.0 * nd[0] * s.px * ((qy ? 0.0 : nd[1] * vy) + (qz ? 0.0 : nd[2] * vz));
     L.c = nd[1] * nd[1] * vy * vy + nd[2] * nd[2] * vz * vz + ((qy || qz) ? 0.0 : 2.0 * nd[1] * nd[2] * vy * vz);
     const int ay = sy < 0 ? -sy : sy;
-    L.stride = (long)(s.ny + 1) * (s.nz + 1);
-    L.row = s.uhat + (long)ay * (s.nz + 1) + kz;
+    L.row = s.uhat + ((long)ay * (s.nz + 1) + kz) * (s.nx + 1);
     L.scale = s.scale;
     L.nx = s.nx;
     return L;
@@ -73,7 +70,7 @@ __device__ __forceinline__ double sym_eval(const SymLine& L, int kx) {
     const int sx = kx < L.nx ? kx : kx - 2 * L.nx;
     const double v = (double)sx;
     const double nn = (L.a * v + (kx == L.nx ? 0.0 : L.b)) * v + L.c;
-    const double u = L.row[(long)(sx < 0 ? -sx : sx) * L.stride];
+    const double u = L.row[sx < 0 ? -sx : sx];
     return (3.0 * nn * u - 1.0) * L.scale;
 }
 
@@ -186,16 +183,18 @@ __global__ void k_sym_tables(const double* __restrict__ s_nodes, int ms, int nk,
     T[(long)m * nk + k] = val;
 }
 
-// U[kx][ky][kz] = sum_m c_m Tx[m][kx] Ty[m][ky] Tz[m][kz] (compensated summation over m).
+// U = sum_m c_m Tx[m][kx] Ty[m][ky] Tz[m][kz] (compensated summation over m), stored in the
+// working layout [ky][kz][kx] (kx fastest): the x passes then read, for each of their columns
+// (ky, kz), one contiguous row over kx.
 __global__ void k_sym_contract(const double* __restrict__ c, int ms, const double* __restrict__ Tx,
                                const double* __restrict__ Ty, const double* __restrict__ Tz, int nkx, int nky, int nkz,
                                double* __restrict__ U) {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long tot = (long)nkx * nky * nkz;
     if (id >= tot) return;
-    const int kz = (int)(id % nkz);
-    const int ky = (int)((id / nkz) % nky);
-    const int kx = (int)(id / ((long)nkz * nky));
+    const int kx = (int)(id % nkx);
+    const int kz = (int)((id / nkx) % nkz);
+    const int ky = (int)(id / ((long)nkx * nkz));
     double acc = 0.0, comp = 0.0;
     for (int m = 0; m < ms; ++m) {
         const double t = c[m] * Tx[(long)m * nkx + kx] * Ty[(long)m * nky + ky] * Tz[(long)m * nkz + kz] - comp;
@@ -206,10 +205,22 @@ __global__ void k_sym_contract(const double* __restrict__ c, int ms, const doubl
     U[id] = acc;
 }
 
+// working layout [ky][kz][kx] -> octant layout [kx][ky][kz] (the documented output)
+__global__ void k_sym_to_octant(const double* __restrict__ U, int nkx, int nky, int nkz, double* __restrict__ out) {
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long tot = (long)nkx * nky * nkz;
+    if (id >= tot) return;
+    const int kz = (int)(id % nkz);
+    const int ky = (int)((id / nkz) % nky);
+    const int kx = (int)(id / ((long)nkz * nky));
+    out[id] = U[((long)ky * nkz + kz) * nkx + kx];
+}
+
 #include "pcg.inc"
 
 // ------------------------------------------------------------------ fused finalize + control
-// One block per solve. Each segment holds nb per-block partial rows of nq slots at offset `off`
+// One block per solve (or per segment and solve, see gridDim.y). Each segment holds nb per-block
+// partial rows of nq slots at offset `off`
 // of the solve's partial region; every thread sums its rows in order, waves reduce by shuffles,
 // the four wave results are combined in a fixed order into st[b].red[row][q0 + q]. Then one
 // thread runs the control step that consumes the sums (CTL), replacing separate finalize and
@@ -221,7 +232,8 @@ __global__ __launch_bounds__(kThreads) void k_fin(const double* __restrict__ par
     if (st[b].done) return;
     __shared__ double sh[kThreads / 64][kFinQ];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int si = 0; si < L.n; ++si) {
+    // gridDim.y > 1: the segments are shared out over the blocks of a solve (CTL is then FC_NONE)
+    for (int si = blockIdx.y; si < L.n; si += gridDim.y) {
         const FinSeg sg = L.s[si];
         const double* p = partials + b * part_stride + sg.off;
         double acc[kFinQ];
