@@ -85,6 +85,18 @@ struct Layout {
     size_t symscr_doubles;
 };
 
+// Row stride of the z half-spectrum buffers: Nz+1 entries padded to a multiple of 16, so that a
+// tile of 8 (FP64) or 16 (FP32) consecutive kz columns starts on a 128-byte boundary.
+int hs_ld(int nz) { return (nz + 1 + 15) / 16 * 16; }
+
+// Tiles of an x pass over a half-spectrum buffer [Nx][nky][ld]: L consecutive ky at the Nyquist
+// kz = nzq, then L consecutive kz < nzq at one ky.
+void hs_tiles(Geo& g) {
+    g.cpk = (g.nzq + g.L - 1) / g.L;
+    g.nreg = g.nky * g.cpk;
+    g.ntiles = g.nreg + (g.nky + g.L - 1) / g.L;
+}
+
 Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
     Geo g;
     std::memset(&g, 0, sizeof(g));
@@ -107,6 +119,7 @@ Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
         g.L = L;
         g.tpo = (d2 + L - 1) / L;
         g.ntiles = d0 * g.tpo;
+        g.row = d2;
     } else {
         g.n_outer = 1;
         g.n_inner = d1 * d2;
@@ -115,15 +128,43 @@ Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
         g.tpo = (g.n_inner + L - 1) / L;
         g.ntiles = g.tpo;
         g.dB = d2;
+        g.row = g.n_inner;
     }
+    return g;
+}
+
+// Padded y passes over the half-spectrum buffers: lines along y at (x, kz), kz <= nz, rows of ld.
+Geo make_geo_hs_y(int nx, int nz, int nfft) {
+    Geo g = make_geo(1, nx, 0, nz + 1, nfft, 0);
+    g.row = hs_ld(nz);
+    return g;
+}
+
+// Padded x passes over [Nx][nky][ld]: columns (ky, kz), the Nyquist column kz = nz tiled apart.
+Geo make_geo_hs_x(int nky, int nz, int nfft, int dual) {
+    Geo g;
+    std::memset(&g, 0, sizeof(g));
+    g.axis = 0;
+    int L = kTileElems / nfft;
+    if (dual) L /= 2;
+    if (L < 1) L = 1;
+    g.L = L;
+    g.n_outer = 1;
+    g.n_inner = nky * (nz + 1);
+    g.hs = 1;
+    g.nky = nky;
+    g.nzq = nz;
+    g.ld = hs_ld(nz);
+    g.row = (long)nky * g.ld;
+    hs_tiles(g);
     return g;
 }
 
 Layout layout(const int n[3], int precision, int batch) {
     Layout L;
     const size_t N = (size_t)n[0] * n[1] * n[2];
-    const size_t Nz1 = (size_t)n[0] * n[1] * (n[2] + 1);
-    const size_t Ny2 = (size_t)n[0] * 2 * n[1] * (n[2] + 1);
+    const size_t Nz1 = (size_t)n[0] * n[1] * hs_ld(n[2]);
+    const size_t Ny2 = (size_t)n[0] * 2 * n[1] * hs_ld(n[2]);
     // partial sums of one reducing kernel: at most (blocks of the largest pass) x slots; the
     // register-FFT passes use fewer lines per block than the generic ones at small N, so bound
     // by one block per column as well
@@ -164,8 +205,8 @@ Layout layout(const int n[3], int precision, int batch) {
 template <typename R> void carve_fields(Fields<R>& f, char*& p, const int n[3], int batch) {
     const size_t B = (size_t)batch;
     const size_t N = B * n[0] * n[1] * n[2];
-    const size_t Nz1 = B * n[0] * n[1] * (n[2] + 1);
-    const size_t Ny2 = B * n[0] * 2 * n[1] * (n[2] + 1);
+    const size_t Nz1 = B * n[0] * n[1] * hs_ld(n[2]);
+    const size_t Ny2 = B * n[0] * 2 * n[1] * hs_ld(n[2]);
     auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
     f.hphi = (cpx<R>*)take(N * sizeof(cpx<R>));
     f.acc = (cpx<R>*)take(N * sizeof(cpx<R>));
@@ -481,12 +522,12 @@ int bec_init_grid_batched(const bec_grid_desc* desc, int precision, int batch, v
     g->gz = make_geo(2, nx, ny, nz, nz, 0);
     g->gy = make_geo(1, nx, ny, nz, ny, 0);
     g->gx = make_geo(0, nx, ny, nz, nx, 0);
-    g->g_ay = make_geo(1, nx, ny, nz + 1, 2 * ny, 0);
-    g->g_ax = make_geo(0, nx, 2 * ny, nz + 1, 2 * nx, 0);
-    g->g_ax2 = make_geo(0, nx, 2 * ny, nz + 1, 2 * nx, 1);
+    g->g_ay = make_geo_hs_y(nx, nz, 2 * ny);
+    g->g_ax = make_geo_hs_x(2 * ny, nz, 2 * nx, 0);
+    g->g_ax2 = make_geo_hs_x(2 * ny, nz, 2 * nx, 1);
     g->zf_L = std::max(1, kTileElems / (2 * nz));
     const long N = (long)nx * ny * nz;
-    g->bt64 = Bat{N, (long)nx * ny * (nz + 1), (long)nx * 2 * ny * (nz + 1), L.part_stride};
+    g->bt64 = Bat{N, (long)nx * ny * hs_ld(nz), (long)nx * 2 * ny * hs_ld(nz), L.part_stride};
     g->bt32 = g->bt64;
     if (const char* ev = std::getenv("BEC_GENERIC_FFT")) g->use_rf = std::atoi(ev) ? 0 : 1;
     if ((rc = make_plans<double>(*g, g->f64, g->ws + L.tw64))) { delete g; return rc; }

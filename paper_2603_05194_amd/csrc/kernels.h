@@ -15,6 +15,10 @@ struct Geo {
     int tpo;          // tiles per outer (axes 0/1)
     int ntiles;
     int dA, dB;       // axis 2: dA = d1 (to split outer); axis 0: dB = d2 (to split inner)
+    long row;         // axes 0/1: elements between consecutive points of a line
+    // axis 0 over a half-spectrum buffer [Nx][nky][ld] (hs = 1): tiles of L columns ky at the
+    // Nyquist kz = nzq, then tiles of L columns kz < nzq at one ky (cpk per ky, nreg in all)
+    int hs, nky, nzq, ld, cpk, nreg;
 };
 
 // Scalars shared between field kernels and the single-thread control kernels (FP64 always).

@@ -36,3 +36,36 @@ def test_table1_virial_residual(case, om, n):
     print(f"E {r['E']:.12f} |I| {abs(r['virial']):.5e} printed {ref:.5e}")
     assert r["res"] <= 1e-12
     assert abs(abs(r["virial"]) - ref) <= 1e-2 * ref
+
+
+E2_CASES = [("I", "0.2"), ("II", "0.2")]
+
+
+@pytest.mark.parametrize("case,om", E2_CASES)
+def test_table1_relative_error_against_fine_solution(case, om):
+    """E2 of Table 1 for a vortex-free state: ||phi^h - kappa phi_g|| / ||phi_g|| on the coarse
+    grid, with phi_g our 256^3 ground state sampled at the coarse points (the paper's reference
+    is 512^3; at 256^3 the printed error is already ~1e-11, far below the 32^3-128^3 values)."""
+    import numpy as np
+    from paper_2603_05194_amd import guesses as G
+    from tests.gpu_util import host
+    c = GOLD["cases"][case]
+    a, gam = tuple(c["box_half_widths"]), tuple(c["gamma"])
+    o = bec.bec_pcg_default_opts()
+    o.max_iter = 200000
+    o.tol_res_inf = 1e-12
+    print(f"E2 case {case} Omega {om}: 256^3 reference", flush=True)
+    best, ref, _, _ = G.lowest_energy((256, 256, 256), a, gam, 100.0, 80.0, (0.0, 0.0, 1.0), float(om), levels=3,
+                                      precision=bec.BEC_FP64, opts=o)
+    ref = host(ref)
+    for n in (32, 64, 128):
+        best, phi, _, _ = G.lowest_energy((n, n, n), a, gam, 100.0, 80.0, (0.0, 0.0, 1.0), float(om), levels=1,
+                                          precision=bec.BEC_FP64, opts=o)
+        phi = host(phi)
+        s = 256 // n
+        pg = ref[::s, ::s, ::s]
+        kappa = np.vdot(pg, phi) / np.vdot(pg, pg)
+        e2 = np.linalg.norm(phi - kappa * pg) / np.linalg.norm(pg)
+        printed = GOLD["E2"][case][om][str(n)]
+        print(f"N {n}: E2 {e2:.5e} printed {printed:.5e}")
+        assert abs(e2 - printed) <= 2e-2 * printed
