@@ -174,6 +174,15 @@ int bec_normalize(bec_grid g, void* d_phi);
  * sum phi G = 0 is left unchanged. */
 int bec_gauge_fix(bec_grid g, const bec_params* p, void* d_phi);
 
+/* Rotation about the z axis (Sec. 3, rotation-aligned error of vortex states): d_out(x) =
+ * d_in(R_alpha x) for every complex128 field of the batch, R_alpha the rotation by alpha about
+ * z through the box centre, evaluated exactly on the Fourier interpolant by three one-axis
+ * Fourier shears (shear decomposition; angles beyond pi/2 are split into equal parts). Needs
+ * N_x = N_y and a_x = a_y; the field is treated as periodic on the box, so it should have decayed
+ * at the boundary. d_out may equal d_in. Runs with the solves of the handle marked active (it
+ * clears the handle's device state). */
+int bec_rotate_z(bec_grid g, const void* d_in, void* d_out, double alpha);
+
 /* Measurement helper: runs one stage of the hot path `reps` times on the grid's stream and
  * returns the mean duration per run from HIP events (milliseconds). which = 0: the ATKM
  * padded x pass (forward, symbol multiply, inverse); 1: the whole ATKM potential of |phi|^2;

@@ -90,6 +90,7 @@ _SIGS = {
     "bec_interp_spectral": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "bec_normalize": (C.c_int, [C.c_void_p, C.c_void_p]),
     "bec_gauge_fix": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p]),
+    "bec_rotate_z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
     # learned initial guess (include/bec_mlp.h)
     "bec_mlp_last_error": (C.c_char_p, []),
     "bec_mlp_param_count": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
@@ -233,6 +234,10 @@ def bec_normalize(h, d_phi):
 
 def bec_gauge_fix(h, params, d_phi):
     _check(_lib().bec_gauge_fix(h, _params_arg(params), C.c_void_p(d_phi)), "bec_gauge_fix")
+
+
+def bec_rotate_z(h, d_in, d_out, alpha):
+    _check(_lib().bec_rotate_z(h, C.c_void_p(d_in), C.c_void_p(d_out), alpha), "bec_rotate_z")
 
 
 def bec_mlp_param_count(d_in, d_h, d_out) -> int:
@@ -418,6 +423,14 @@ class BecGrid:
         assert phis.numel() == self.batch * self.n[0] * self.n[1] * self.n[2]
         bec_normalize(self.handle, phis.data_ptr())
         return phis
+
+    def rotate_z(self, phis, alpha):
+        """phis(R_alpha x) for the batch (complex128, [batch, Nx, Ny, Nz] or [Nx, Ny, Nz])."""
+        assert phis.is_contiguous() and phis.dtype == self.torch.complex128
+        assert phis.numel() == self.batch * self.n[0] * self.n[1] * self.n[2]
+        out = self.torch.empty_like(phis)
+        bec_rotate_z(self.handle, phis.data_ptr(), out.data_ptr(), float(alpha))
+        return out
 
     def gauge_fix_(self, params_list, phis):
         assert phis.is_contiguous() and phis.dtype == self.torch.complex128

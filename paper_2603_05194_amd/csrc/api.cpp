@@ -682,6 +682,19 @@ int bec_normalize(bec_grid g, void* d_phi) {
     return check_launch(g, "normalize");
 }
 
+int bec_rotate_z(bec_grid g, const void* d_in, void* d_out, double alpha) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_in || !d_out) return fail(BEC_EINVAL, "NULL field pointer");
+    if (g->n[0] != g->n[1] || !(std::fabs(g->a[0] - g->a[1]) <= 1e-12 * g->a[0]))
+        return fail(BEC_EINVAL, "rotation about z needs N_x = N_y and a_x = a_y");
+    if (!std::isfinite(alpha) || std::fabs(alpha) > 8.0 * M_PI) return fail(BEC_EINVAL, "angle must be finite, |alpha| <= 8 pi");
+    hipError_t e = hipMemsetAsync(g->st, 0, g->batch * sizeof(DevState), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "rotate state");
+    launch_rotate(*g, (const cpx<double>*)d_in, (cpx<double>*)d_out, alpha);
+    return check_launch(g, "rotate");
+}
+
 int bec_gauge_fix(bec_grid g, const bec_params* pp, void* d_phi) {
     int rc = check_grid(g);
     if (rc) return rc;

@@ -90,5 +90,6 @@ void launch_to_f64_normalized(Grid& g, const cpx<float>* a, cpx<double>* b);
 void launch_interp(Grid& src, Grid& dst, const void* in, int in_fp32, void* out, int out_fp32);
 void launch_normalize(Grid& g, cpx<double>* phi);
 void launch_gauge(Grid& g, cpx<double>* phi);
+void launch_rotate(Grid& g, const cpx<double>* in, cpx<double>* out, double alpha);
 
 }  // namespace bec
