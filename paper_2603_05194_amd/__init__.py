@@ -481,7 +481,6 @@ class Mlp:
                            self.w3t.data_ptr(), self.grads.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._scratch = None
-        self._scratch_batch = 0
         self.step_count = 0
 
     def offsets(self):
@@ -505,10 +504,10 @@ class Mlp:
         bec_mlp_sync(self.net, self.stream.cuda_stream)
 
     def scratch(self, batch):
-        if self._scratch is None or self._scratch_batch < batch:
-            nbytes = bec_mlp_scratch_bytes(self.net, batch)
+        """Scratch for `batch` rows; the need is not monotone in the batch, so it is asked each time."""
+        nbytes = bec_mlp_scratch_bytes(self.net, batch)
+        if self._scratch is None or self._scratch.numel() < nbytes:
             self._scratch = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
-            self._scratch_batch = batch
         return self._scratch
 
     def forward(self, x, idx=None, batch=None):

@@ -18,8 +18,11 @@
 namespace bec_mlp_impl {
 
 constexpr int kT = 256;  // threads per block
-constexpr int GBM = 128, GBN = 128, GBK = 32, GPAD = 8;
-constexpr int kLossBlocks = 1024;
+constexpr int GBM = 128, GBN = 128, GBK = 64, GPAD = 8;
+constexpr int kSK = GBK / 8;                // threads per staged row (8 BF16 each)
+constexpr int kSR = kT / kSK;               // rows staged per pass
+constexpr int kSP = GBM / kSR;              // passes per operand tile
+constexpr int kMaxGroups = 64;     // row groups of the batch reductions
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -34,6 +37,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ------------------------------------------------------------------ GEMM (matrix cores)
+// 8 BF16 of row min(r, rows - 1) at column kc (an in-range address for any r).
+__device__ __forceinline__ uint4 ld_row(const uint16_t* __restrict__ p, int ld, int r, int rows, int kc) {
+    return *(const uint4*)(p + (size_t)min(r, rows - 1) * ld + kc);
+}
+
 // Block tile 128 x 128, K step 32; four waves in a 2 x 2 layout, each owning a 64 x 64 sub-tile
 // of 2 x 2 MFMA 32x32 accumulators. MFMA 32x32x16 bf16 operand layout: lane l supplies row
 // (l mod 32) of A (resp. column of B) and k = 8 (l div 32) + 0..7; accumulator register r of
@@ -57,26 +65,30 @@ __global__ __launch_bounds__(kT) void k_gemm_nt(int M, int N, int K, int kper, c
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    uint4 ra[2], rb[2];
+    // Thread tid stages rows tid/kSK + p kSR (p < kSP) of each operand tile at k offset
+    // 8 (tid mod kSK); the next K step is loaded into registers while this one is multiplied.
+    // Out-of-range rows and k are loaded from a clamped in-range address and zeroed by a mask
+    // when written to LDS, so every load is unconditional and the stage stays in registers.
+    const int srow = tid / kSK, sk = (tid % kSK) * 8;
+    uint4 ra[kSP], rb[kSP];
     auto gload = [&](int k0) {
+        const int kc = min(k0 + sk, ke - 8);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int c = tid + kT * i;
-            const int row = c >> 2, k = k0 + (c & 3) * 8;
-            const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-            ra[i] = (m0 + row < M && k < ke) ? *(const uint4*)(A + (size_t)(m0 + row) * lda + k) : z;
-            rb[i] = (n0 + row < N && k < ke) ? *(const uint4*)(B + (size_t)(n0 + row) * ldb + k) : z;
+        for (int p = 0; p < kSP; ++p) {
+            ra[p] = ld_row(A, lda, m0 + p * kSR + srow, M, kc);
+            rb[p] = ld_row(B, ldb, n0 + p * kSR + srow, N, kc);
         }
     };
     if (kb < ke) gload(kb);
     for (int k0 = kb; k0 < ke; k0 += GBK) {
         __syncthreads();
+        const bool kok = k0 + sk < ke;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int c = tid + kT * i;
-            const int row = c >> 2, kc = (c & 3) * 8;
-            *(uint4*)&As[row][kc] = ra[i];
-            *(uint4*)&Bs[row][kc] = rb[i];
+        for (int p = 0; p < kSP; ++p) {
+            const uint32_t ma = (kok && m0 + p * kSR + srow < M) ? 0xffffffffu : 0u;
+            const uint32_t mb = (kok && n0 + p * kSR + srow < N) ? 0xffffffffu : 0u;
+            *(uint4*)&As[p * kSR + srow][sk] = make_uint4(ra[p].x & ma, ra[p].y & ma, ra[p].z & ma, ra[p].w & ma);
+            *(uint4*)&Bs[p * kSR + srow][sk] = make_uint4(rb[p].x & mb, rb[p].y & mb, rb[p].z & mb, rb[p].w & mb);
         }
         __syncthreads();
         if (k0 + GBK < ke) gload(k0 + GBK);
@@ -110,24 +122,39 @@ __global__ __launch_bounds__(kT) void k_gemm_nt(int M, int N, int K, int kper, c
         }
 }
 
-// C[m][n] = sum_z part[z][m][n] (fixed order) + bias[n]
+// C[m][n] = sum_z part[z][m][n] + bias[n]. A block covers 64 consecutive elements; its four
+// waves sum consecutive quarters of the z range, which are then added in order (deterministic).
 __global__ __launch_bounds__(kT) void k_split_sum(const float* __restrict__ part, int S, int M, int N,
                                                   float* __restrict__ C, int ldc, const float* __restrict__ bias) {
+    __shared__ float q[4][64];
     const long MN = (long)M * N;
-    for (long i = (long)blockIdx.x * kT + threadIdx.x; i < MN; i += (long)gridDim.x * kT) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int zq = (S + 3) / 4, z0 = w * zq, z1 = min(S, z0 + zq);
+    for (long base = (long)blockIdx.x * 64; base < MN; base += (long)gridDim.x * 64) {
+        const long i = base + lane;
         float s = 0.0f;
-        for (int z = 0; z < S; ++z) s += part[z * MN + i];
-        const int n = (int)(i % N), m = (int)(i / N);
-        C[(size_t)m * ldc + n] = s + (bias ? bias[n] : 0.0f);
+        if (i < MN)
+            for (int z = z0; z < z1; ++z) s += part[z * MN + i];
+        q[w][lane] = s;
+        __syncthreads();
+        if (w == 0 && i < MN) {
+            const float v = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
+            const int n = (int)(i % N), m = (int)(i / N);
+            C[(size_t)m * ldc + n] = v + (bias ? bias[n] : 0.0f);
+        }
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ elementwise kernels
 // dst[c][r] = src[r][c] for r < R, zero for R <= r < Rp (c < Cn); 64 x 64 tiles through LDS.
+// blockIdx.x runs along the longer of the two dimensions (rows if x_rows), so that blocks in
+// flight together read and write neighbouring addresses rather than one column of rows a large
+// power of two apart.
 __global__ __launch_bounds__(kT) void k_transpose_bf16(const uint16_t* __restrict__ src, int R, int Cn, int lds_,
-                                                       uint16_t* __restrict__ dst, int Rp, int ldd) {
+                                                       uint16_t* __restrict__ dst, int Rp, int ldd, int x_rows) {
     __shared__ uint16_t t[64][65];
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int r0 = (x_rows ? blockIdx.x : blockIdx.y) * 64, c0 = (x_rows ? blockIdx.y : blockIdx.x) * 64;
     for (int e = threadIdx.x; e < 64 * 64; e += kT) {
         const int r = e >> 6, c = e & 63;
         const int gr = r0 + r, gc = c0 + c;
@@ -172,84 +199,123 @@ __global__ __launch_bounds__(kT) void k_tanh(float* __restrict__ t, uint16_t* __
     }
 }
 
-// d = g * (1 - t^2) (tanh derivative), in place on g; BF16 copy to db (nullable).
-__global__ __launch_bounds__(kT) void k_dtanh(float* __restrict__ g, const float* __restrict__ t, uint16_t* __restrict__ db,
-                                              long n) {
-    for (long i = (long)blockIdx.x * kT + threadIdx.x; i < n; i += (long)gridDim.x * kT) {
-        const float v = g[i] * (1.0f - t[i] * t[i]);
-        g[i] = v;
-        if (db) db[i] = f2bf(v);
-    }
-}
+// Column reductions over the batch are done in two passes: a grid of (column chunk, row group)
+// blocks, one thread per column summing its rows in order into part[group][column] (FP64), then
+// k_col_finish adding the groups in order. Both passes are deterministic.
 
-// dY = s (y - target[idx[b]]) as BF16; per-block FP64 sums of (y - target)^2.
-__global__ __launch_bounds__(kT) void k_mse(int batch, int dout, const float* __restrict__ y, const float* __restrict__ tg,
-                                            const int32_t* __restrict__ idx, float s, uint16_t* __restrict__ dyb,
-                                            double* __restrict__ part) {
-    const long tot = (long)batch * dout;
-    double acc = 0.0;
-    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < tot; e += (long)gridDim.x * kT) {
-        const int o = (int)(e % dout), b = (int)(e / dout);
-        const long row = idx ? idx[b] : b;
-        const float d = y[e] - tg[row * dout + o];
-        acc += (double)d * d;
-        dyb[e] = f2bf(s * d);
-    }
+// Block sum of one double per thread (fixed tree); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
     __shared__ double red[kT / 64];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double v = 0.0;
-        for (int i = 0; i < kT / 64; ++i) v += red[i];
-        part[blockIdx.x] = v;
-    }
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kT / 64; ++i) r += red[i];
+    return r;
 }
 
-__global__ void k_loss_final(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double v = 0.0;
-        for (int i = 0; i < n; ++i) v += part[i];
-        *out = v * scale;
+// Output layer, rows [g rpg, (g+1) rpg) of column o: dY = s (y - target[idx[b]]) as BF16,
+// colpart[g][o] = sum_b (y - target) and per-block sums of (y - target)^2 into sqpart.
+__global__ __launch_bounds__(kT) void k_out_grad(int batch, int dout, int rpg, const float* __restrict__ y,
+                                                 const float* __restrict__ tg, const int32_t* __restrict__ idx, float s,
+                                                 uint16_t* __restrict__ dyb, double* __restrict__ colpart,
+                                                 double* __restrict__ sqpart) {
+    const int o = blockIdx.x * kT + threadIdx.x, g = blockIdx.y;
+    const int b0 = g * rpg, b1 = min(batch, b0 + rpg);
+    double sq = 0.0;
+    if (o < dout) {
+        double cs = 0.0;
+#pragma unroll 4
+        for (int b = b0; b < b1; ++b) {
+            const long row = idx ? idx[b] : b;
+            const float d = y[(size_t)b * dout + o] - tg[row * dout + o];
+            cs += (double)d;
+            sq += (double)d * d;
+            dyb[(size_t)b * dout + o] = f2bf(s * d);
+        }
+        colpart[(size_t)g * dout + o] = cs;
     }
+    const double t = block_sum(sq);
+    if (threadIdx.x == 0) sqpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
-// gb[o] = s * sum_b (y[b][o] - target[idx[b]][o])  (bias gradient of the output layer)
-__global__ __launch_bounds__(kT) void k_colsum_out(int batch, int dout, const float* __restrict__ y,
-                                                   const float* __restrict__ tg, const int32_t* __restrict__ idx, float s,
-                                                   float* __restrict__ gb) {
-    const int o = blockIdx.x * kT + threadIdx.x;
-    if (o >= dout) return;
-    double acc = 0.0;
-    for (int b = 0; b < batch; ++b) {
-        const long row = idx ? idx[b] : b;
-        acc += (double)(y[(size_t)b * dout + o] - tg[row * dout + o]);
-    }
-    gb[o] = (float)(s * acc);
-}
-
-// gb[o] = sum_b d[b][o]
-__global__ __launch_bounds__(kT) void k_colsum(int batch, int n, const float* __restrict__ d, float* __restrict__ gb) {
-    const int o = blockIdx.x * kT + threadIdx.x;
+// Hidden layer 2, rows [g rpg, (g+1) rpg) of column o: d = g (1 - t^2) in place, BF16 copy to db,
+// colpart[g][o] = sum_b d.
+__global__ __launch_bounds__(kT) void k_dtanh_cols(int batch, int n, int rpg, float* __restrict__ gr,
+                                                   const float* __restrict__ t, uint16_t* __restrict__ db,
+                                                   double* __restrict__ colpart) {
+    const int o = blockIdx.x * kT + threadIdx.x, g = blockIdx.y;
     if (o >= n) return;
-    double acc = 0.0;
-    for (int b = 0; b < batch; ++b) acc += d[(size_t)b * n + o];
-    gb[o] = (float)acc;
+    const int b0 = g * rpg, b1 = min(batch, b0 + rpg);
+    double cs = 0.0;
+#pragma unroll 4
+    for (int b = b0; b < b1; ++b) {
+        const size_t e = (size_t)b * n + o;
+        const float tv = t[e];
+        const float v = gr[e] * (1.0f - tv * tv);
+        gr[e] = v;
+        db[e] = f2bf(v);
+        cs += (double)v;
+    }
+    colpart[(size_t)g * n + o] = cs;
 }
 
-// gW1[o][i] = sum_b d1[b][o] x[idx[b]][i]
-__global__ __launch_bounds__(kT) void k_gw1(int batch, int din, int dh, const float* __restrict__ d1,
-                                            const float* __restrict__ x, const int32_t* __restrict__ idx,
-                                            float* __restrict__ gw) {
-    const int e = blockIdx.x * kT + threadIdx.x;
-    if (e >= dh * din) return;
-    const int o = e / din, i = e % din;
-    double acc = 0.0;
-    for (int b = 0; b < batch; ++b) {
-        const long row = idx ? idx[b] : b;
-        acc += (double)d1[(size_t)b * dh + o] * x[row * din + i];
+// Hidden layer 1, rows [g rpg, (g+1) rpg) of unit o: d1 = g (1 - t^2) (FP32),
+// colpart[g][o] = sum_b d1 and wpart[g][o][i] = sum_b d1 x[idx[b]][i], inputs in chunks of 8.
+__global__ __launch_bounds__(kT) void k_d1_cols(int batch, int din, int dh, int rpg, const float* __restrict__ gr,
+                                                const float* __restrict__ t, const float* __restrict__ x,
+                                                const int32_t* __restrict__ idx, double* __restrict__ colpart,
+                                                double* __restrict__ wpart) {
+    const int o = blockIdx.x * kT + threadIdx.x, g = blockIdx.y;
+    if (o >= dh) return;
+    const int b0 = g * rpg, b1 = min(batch, b0 + rpg);
+    double cs = 0.0;
+    for (int c0 = 0; c0 < din; c0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+        for (int b = b0; b < b1; ++b) {
+            const size_t e = (size_t)b * dh + o;
+            const float tv = t[e];
+            const float v = gr[e] * (1.0f - tv * tv);
+            if (c0 == 0) cs += (double)v;
+            const float* xr = x + (size_t)(idx ? idx[b] : b) * din + c0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (c0 + j < din) acc[j] += (double)v * xr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (c0 + j < din) wpart[((size_t)g * dh + o) * din + c0 + j] = acc[j];
     }
-    gw[e] = (float)acc;
+    colpart[(size_t)g * dh + o] = cs;
+}
+
+// out[o] = scale * sum_g part[g][o]. A block covers 64 columns; its four waves sum consecutive
+// quarters of the groups, which are then added in order (deterministic).
+__global__ __launch_bounds__(kT) void k_col_finish(int n, int groups, const double* __restrict__ part, double scale,
+                                                   float* __restrict__ out) {
+    __shared__ double q[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
+    const int gq = (groups + 3) / 4, g0 = w * gq, g1 = min(groups, g0 + gq);
+    double v = 0.0;
+    if (o < n)
+#pragma unroll 4
+        for (int g = g0; g < g1; ++g) v += part[(size_t)g * n + o];
+    q[w][lane] = v;
+    __syncthreads();
+    if (w == 0 && o < n) out[o] = (float)(scale * (((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane]));
+}
+
+// *out = scale * sum_i part[i]: one block, strided per-thread sums then a fixed tree.
+__global__ __launch_bounds__(kT) void k_loss_final(const double* __restrict__ part, int n, double scale,
+                                                   double* __restrict__ out) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += kT) v += part[i];
+    const double t = block_sum(v);
+    if (threadIdx.x == 0) *out = t * scale;
 }
 
 // Adam (FP32). Every coefficient comes from the host, rounded once from FP64:
@@ -281,6 +347,21 @@ int grid1(long n) {
     long b = (n + kT * 4 - 1) / (kT * 4);
     if (b > 4096) b = 4096;
     return (int)(b < 1 ? 1 : b);
+}
+
+// Upper bound of row_groups(B, cols), non-decreasing in B: scratch is sized by it.
+int group_cap(int B, int cols) {
+    const int cb = (cols + kT - 1) / kT;
+    return std::min(B, std::min(kMaxGroups, (1024 + cb - 1) / cb));
+}
+
+// Row groups for a batch reduction over `cols` columns: about 1024 blocks in all, at most
+// kMaxGroups groups and none empty. *rpg receives the rows per group.
+int row_groups(int B, int cols, int* rpg) {
+    const int G = group_cap(B, cols);
+    const int r = (B + G - 1) / G;
+    *rpg = r;
+    return (B + r - 1) / r;
 }
 
 struct Offs {
@@ -323,7 +404,8 @@ void gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int lda, const 
     } else {
         hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kT), 0, s, M, N, K, kper, A, lda, B, ldb, part, N, (long)M * N,
                            (const float*)nullptr);
-        hipLaunchKernelGGL(k_split_sum, dim3(grid1((long)M * N)), dim3(kT), 0, s, (const float*)part, S, M, N, C, ldc, bias);
+        const long blocks = std::min(((long)M * N + 63) / 64, 65536L);
+        hipLaunchKernelGGL(k_split_sum, dim3((unsigned)blocks), dim3(kT), 0, s, (const float*)part, S, M, N, C, ldc, bias);
     }
 }
 
@@ -354,7 +436,7 @@ size_t al(size_t x) { return (x + 255) / 256 * 256; }
 struct Scratch {
     float *t1, *t2, *z, *y, *part, *d2;
     uint16_t *h1b, *h1bT, *h2b, *h2bT, *dyb, *dybT, *d2b, *d2bT;
-    double* lossp;
+    double *colp, *wp, *lossp;
     size_t bytes;
 };
 
@@ -386,14 +468,18 @@ Scratch carve(const bec_mlp* n, int B, char* base) {
     s.dybT = (uint16_t*)take(2 * (size_t)D * Bp);
     s.d2b = (uint16_t*)take(2 * (size_t)B * dh);
     s.d2bT = (uint16_t*)take(2 * (size_t)dh * Bp);
-    s.lossp = (double*)take(sizeof(double) * kLossBlocks);
+    const int Gd = group_cap(B, D), Gh = group_cap(B, dh);
+    s.colp = (double*)take(sizeof(double) * std::max((size_t)Gd * D, (size_t)Gh * dh));
+    s.wp = (double*)take(sizeof(double) * (size_t)Gh * dh * n->d_in);
+    s.lossp = (double*)take(sizeof(double) * (size_t)Gd * ((D + kT - 1) / kT));
     s.bytes = off;
     return s;
 }
 
 void transpose(hipStream_t st, const uint16_t* src, int R, int Cn, int lds_, uint16_t* dst, int Rp, int ldd) {
-    dim3 grid((Cn + 63) / 64, (Rp + 63) / 64);
-    hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(kT), 0, st, src, R, Cn, lds_, dst, Rp, ldd);
+    const int cb = (Cn + 63) / 64, rb = (Rp + 63) / 64, x_rows = rb > cb;
+    dim3 grid(x_rows ? rb : cb, x_rows ? cb : rb);
+    hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(kT), 0, st, src, R, Cn, lds_, dst, Rp, ldd, x_rows);
 }
 
 void refresh_transposes(const bec_mlp* n, hipStream_t st) {
@@ -478,27 +564,30 @@ int bec_mlp_loss_grad(const bec_mlp* net, int batch, const float* d_x, const flo
     forward(net, B, d_x, d_idx, y, s, st);
     const float sc = (float)(2.0 / ((double)B * D));
     // output layer: dY (BF16), loss, bias gradient, weight gradient gW3 = dY^T h2
-    hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kT), 0, st, B, D, (const float*)y, d_target, d_idx, sc, s.dyb, s.lossp);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, (const double*)s.lossp, kLossBlocks, 1.0 / ((double)B * D),
+    int rd = 0, rh = 0;
+    const int Gd = row_groups(B, D, &rd), Gh = row_groups(B, dh, &rh);
+    const int cbd = (D + kT - 1) / kT, cbh = (dh + kT - 1) / kT;
+    hipLaunchKernelGGL(k_out_grad, dim3(cbd, Gd), dim3(kT), 0, st, B, D, rd, (const float*)y, d_target, d_idx, sc, s.dyb,
+                       s.colp, s.lossp);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kT), 0, st, (const double*)s.lossp, cbd * Gd, 1.0 / ((double)B * D),
                        d_loss);
-    hipLaunchKernelGGL(k_colsum_out, dim3((D + kT - 1) / kT), dim3(kT), 0, st, B, D, (const float*)y, d_target, d_idx, sc,
-                       g + o.b3);
+    hipLaunchKernelGGL(k_col_finish, dim3((D + 63) / 64), dim3(kT), 0, st, D, Gd, (const double*)s.colp, (double)sc, g + o.b3);
     transpose(st, s.dyb, B, D, D, s.dybT, Bp, Bp);
     transpose(st, s.h2b, B, dh, dh, s.h2bT, Bp, Bp);
     transpose(st, s.h1b, B, dh, dh, s.h1bT, Bp, Bp);
     gemm_auto(st, D, dh, Bp, s.dybT, Bp, s.h2bT, Bp, g + o.w3, dh, nullptr, s.part);
     // hidden layer 2: dH2 = dY W3, dA2 = dH2 (1 - t2^2)
     gemm_auto(st, B, dh, D, s.dyb, D, net->w3t_bf16, D, s.z, dh, nullptr, s.part);
-    hipLaunchKernelGGL(k_dtanh, dim3(grid1((long)B * dh)), dim3(kT), 0, st, s.z, (const float*)s.t2, s.d2b, (long)B * dh);
-    hipLaunchKernelGGL(k_colsum, dim3((dh + kT - 1) / kT), dim3(kT), 0, st, B, dh, (const float*)s.z, g + o.b2);
+    hipLaunchKernelGGL(k_dtanh_cols, dim3(cbh, Gh), dim3(kT), 0, st, B, dh, rh, s.z, (const float*)s.t2, s.d2b, s.colp);
+    hipLaunchKernelGGL(k_col_finish, dim3((dh + 63) / 64), dim3(kT), 0, st, dh, Gh, (const double*)s.colp, 1.0, g + o.b2);
     transpose(st, s.d2b, B, dh, dh, s.d2bT, Bp, Bp);
     gemm_auto(st, dh, dh, Bp, s.d2bT, Bp, s.h1bT, Bp, g + o.w2, dh, nullptr, s.part);
     // hidden layer 1: dH1 = dA2 W2, dA1 = dH1 (1 - t1^2) (FP32), gW1 = dA1^T x
     gemm_auto(st, B, dh, dh, s.d2b, dh, net->w2t_bf16, dh, s.d2, dh, nullptr, s.part);
-    hipLaunchKernelGGL(k_dtanh, dim3(grid1((long)B * dh)), dim3(kT), 0, st, s.d2, (const float*)s.t1, (uint16_t*)nullptr,
-                       (long)B * dh);
-    hipLaunchKernelGGL(k_colsum, dim3((dh + kT - 1) / kT), dim3(kT), 0, st, B, dh, (const float*)s.d2, g + o.b1);
-    hipLaunchKernelGGL(k_gw1, dim3((dh * din + kT - 1) / kT), dim3(kT), 0, st, B, din, dh, (const float*)s.d2, d_x, d_idx,
+    hipLaunchKernelGGL(k_d1_cols, dim3(cbh, Gh), dim3(kT), 0, st, B, din, dh, rh, (const float*)s.d2, (const float*)s.t1,
+                       d_x, d_idx, s.colp, s.wp);
+    hipLaunchKernelGGL(k_col_finish, dim3((dh + 63) / 64), dim3(kT), 0, st, dh, Gh, (const double*)s.colp, 1.0, g + o.b1);
+    hipLaunchKernelGGL(k_col_finish, dim3((dh * din + 63) / 64), dim3(kT), 0, st, dh * din, Gh, (const double*)s.wp, 1.0,
                        g + o.w1);
     return launch_status("mlp loss_grad");
 }

@@ -278,9 +278,36 @@ def load(path):
     return net
 
 
+def time_step(batch=256, steps=50, warmup=3):
+    """Wall time of one training step (loss gradient + Adam) of the shipped architecture on a
+    synthetic batch; returns seconds per step and the GEMM rate over the step."""
+    import bec_inputs as bi
+    import torch
+    net = Mlp(*DIMS)
+    net.load_params(bi.mlp_init(DIMS, 0))
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.uniform(-1, 1, (batch, DIMS[0])).astype(np.float32)).to(net.device)
+    t = torch.from_numpy((0.01 * rng.standard_normal((batch, DIMS[2]))).astype(np.float32)).to(net.device)
+    for _ in range(warmup):
+        net.loss_grad(x, t)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.loss_grad(x, t)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    d_in, d_h, d_out = DIMS
+    flops = 3 * 2 * batch * (d_h * d_h + d_h * d_out)   # forward + two backward products per layer
+    return dict(batch=batch, steps=steps, ms_per_step=dt * 1e3, gemm_tflops=flops / dt / 1e12)
+
+
 def main(argv=None):
     import bec_inputs as bi
     ap = argparse.ArgumentParser()
+    ap.add_argument("--time-step", type=int, default=0, metavar="B",
+                    help="only time training steps at batch B on a synthetic batch and exit")
     ap.add_argument("--train", type=int, default=2000, help="training draws (seeds 0..)")
     ap.add_argument("--val", type=int, default=64, help="held-out draws (seeds 10^6..)")
     ap.add_argument("--max-iter", type=int, default=4000)
@@ -292,6 +319,9 @@ def main(argv=None):
     ap.add_argument("--drop", type=float, default=1e-2, help="drop draws with boundary |phi| above this x max")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    if args.time_step:
+        print(json.dumps(time_step(args.time_step)), flush=True)
+        return
     log = lambda s: print(s, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     draws = [bi.mlp_param_draw(s) for s in range(args.train)]

@@ -161,3 +161,22 @@ def test_short_training_run_tracks_oracle():
     assert gl[-1] < 0.5 * gl[0]
     assert abs(gl[0] - ol[0]) <= 1e-5 * ol[0]
     assert np.all(np.abs(np.array(gl) - np.array(ol)) <= 3e-2 * np.array(ol))
+
+
+def test_gradients_across_batch_sizes_on_one_network():
+    """One network called at batch sizes whose row grouping and split-K plans differ (and whose
+    scratch need is not monotone in the batch): every call matches the oracle."""
+    torch = torch_mod()
+    dims = (6, 64, 256)
+    net, p = make_net(dims, 13)
+    for B in (9, 8, 1, 129, 128, 300):
+        x, t = batch_inputs(B, dims, 100 + B)
+        print(f"mlp loss_grad dims={dims} B={B}", flush=True)
+        loss = net.loss_grad(dev(x), dev(t))
+        torch.cuda.synchronize()
+        g = host(net.grads).astype(np.float64)
+        ref_loss, ref_g, _ = om.loss_grad(p, x, t, dims, bf16=True)
+        assert abs(host(loss)[0] - ref_loss) <= 1e-5 * ref_loss
+        for k, (a, b) in net.offsets().items():
+            err = np.linalg.norm(g[a:b] - ref_g[a:b]) / np.linalg.norm(ref_g[a:b])
+            assert err <= 1e-3, (B, k, err)
