@@ -82,8 +82,9 @@ int bec_mlp_adam_step(const bec_mlp* net, double lr, double beta1, double beta2,
  *   C[m][n] = sum_k A[m][k] B[n][k] (+ bias[n])   for m < M, n < N
  * A: BF16 [M][lda], B: BF16 [N][ldb] (both K-contiguous), C: FP32 [M][ldc]. K, lda, ldb must
  * be multiples of 8 and the pointers 16-byte aligned. With splits > 1 the K range is cut into
- * `splits` parts whose partial products go to d_part (FP32, splits*M*N) and are summed in a
- * fixed order; d_part may be NULL when splits == 1. bias may be NULL. */
+ * at most `splits` parts, each a multiple of 64 long (the kernel's K step); their partial
+ * products go to d_part (FP32, splits*M*N) and are summed in a fixed order. d_part may be NULL
+ * when that leaves a single part (always when splits == 1). bias may be NULL. */
 int bec_gemm_bf16_nt(int M, int N, int K, const uint16_t* d_A, int lda, const uint16_t* d_B, int ldb,
                      float* d_C, int ldc, const float* d_bias, int splits, float* d_part, void* stream);
 

@@ -78,7 +78,7 @@ def test_mlp_abi_validation_without_gpu():
     g = lib.bec_gemm_bf16_nt
     assert g(4, 4, 12, C.c_void_p(256), 16, C.c_void_p(256), 16, C.c_void_p(256), 4, None, 1, None, None) == bec.BEC_EINVAL
     assert g(4, 4, 16, C.c_void_p(258), 16, C.c_void_p(256), 16, C.c_void_p(256), 4, None, 1, None, None) == bec.BEC_EINVAL
-    assert g(4, 4, 64, C.c_void_p(256), 64, C.c_void_p(256), 64, C.c_void_p(256), 4, None, 2, None, None) == bec.BEC_EINVAL
+    assert g(4, 4, 256, C.c_void_p(256), 256, C.c_void_p(256), 256, C.c_void_p(256), 4, None, 2, None, None) == bec.BEC_EINVAL
 
 
 def test_interp_validation_without_gpu():
