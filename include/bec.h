@@ -192,6 +192,25 @@ int bec_rotate_z(bec_grid g, const void* d_in, void* d_out, double alpha);
  * Synchronises. */
 int bec_time_stage(bec_grid g, const bec_params* p, const void* d_phi, int which, int reps, double* avg_ms);
 
+/* Line tiles of the runtime-length FFT kernels (lengths other than 32..1024 powers of two, or
+ * every length when the register kernels are switched off). These kernels hold one tile of at
+ * most 4096 complex values per block, 2048 for two-field passes. div[a] (a = 0: x, 1: y, 2: z)
+ * divides the number of lines per block of every pass along axis a, padded passes included.
+ * div[a] must be a power of two in [1, 16]; the default is 1. Tiles change the partition of the
+ * lines among blocks and the order of the block partial sums, nothing else: fields are
+ * unchanged bit for bit, and reductions change at rounding level. A project addition
+ * (performance only, no passage of the paper). Takes effect from the next call on the handle. */
+int bec_set_line_tiles(bec_grid g, const int32_t div[3]);
+/* Current divisors; tunable (nullable) receives 1 for the axes that run a runtime-length pass. */
+int bec_get_line_tiles(bec_grid g, int32_t div[3], int32_t tunable[3]);
+/* Searches the divisors one axis at a time (z, y, x) over 1, 2, 4, 8, 16. Each candidate is
+ * timed with HIP events as one H phi apply plus one two-density padded x Parseval pass on d_phi
+ * and p, `reps` runs after a warm-up. Leaves the fastest set on the grid and returns it in
+ * div_out (nullable) with its time in ms_out (nullable). Axes without a runtime-length pass are
+ * skipped. Needs bec_atkm_symbol. Synchronises. */
+int bec_autotune_line_tiles(bec_grid g, const bec_params* p, const void* d_phi, int reps, int32_t div_out[3],
+                            double* ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,10 @@ _SIGS = {
     "bec_normalize": (C.c_int, [C.c_void_p, C.c_void_p]),
     "bec_gauge_fix": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p]),
     "bec_rotate_z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    "bec_set_line_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "bec_get_line_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "bec_autotune_line_tiles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_double)]),
     # learned initial guess (include/bec_mlp.h)
     "bec_mlp_last_error": (C.c_char_p, []),
     "bec_mlp_param_count": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
@@ -221,6 +225,25 @@ def bec_time_stage(h, params, d_phi, which, reps) -> float:
     ms = C.c_double(0.0)
     _check(_lib().bec_time_stage(h, _params_arg(params), C.c_void_p(d_phi), which, reps, C.byref(ms)), "bec_time_stage")
     return ms.value
+
+
+def bec_set_line_tiles(h, div):
+    arr = (C.c_int32 * 3)(*[int(v) for v in div])
+    _check(_lib().bec_set_line_tiles(h, arr), "bec_set_line_tiles")
+
+
+def bec_get_line_tiles(h):
+    """(divisors, tunable flags), each a tuple over (x, y, z)."""
+    d, t = (C.c_int32 * 3)(), (C.c_int32 * 3)()
+    _check(_lib().bec_get_line_tiles(h, d, t), "bec_get_line_tiles")
+    return tuple(d), tuple(t)
+
+
+def bec_autotune_line_tiles(h, params, d_phi, reps):
+    d, ms = (C.c_int32 * 3)(), C.c_double(0.0)
+    _check(_lib().bec_autotune_line_tiles(h, _params_arg(params), C.c_void_p(d_phi), reps, d, C.byref(ms)),
+           "bec_autotune_line_tiles")
+    return tuple(d), ms.value
 
 
 def bec_interp_spectral(h_src, h_dst, d_in, in_precision, d_out, out_precision):
@@ -404,6 +427,55 @@ class BecGrid:
     def time_stage(self, params, phi, which, reps=10):
         self.ensure_symbol()
         return bec_time_stage(self.handle, params, self._field(phi).data_ptr(), which, reps)
+
+    def set_line_tiles(self, div):
+        """Per-axis (x, y, z) divisors of the runtime-length FFT kernels' lines per block."""
+        bec_set_line_tiles(self.handle, div)
+
+    def line_tiles(self):
+        """((div_x, div_y, div_z), (tunable_x, tunable_y, tunable_z))."""
+        return bec_get_line_tiles(self.handle)
+
+    def tile_key(self):
+        torch = self.torch
+        dev = torch.cuda.get_device_name(self.device)
+        prec = "fp64" if self.precision == BEC_FP64 else "fp32"
+        return f"{dev}|{prec}|{self.n[0]}x{self.n[1]}x{self.n[2]}|batch{self.batch}"
+
+    def autotune(self, params, phis, reps=5, cache=None, log=None):
+        """Search the line tiles (bec_autotune_line_tiles) on `phis` (one field, or [batch, ...] for
+        a batched grid, in the grid's precision) and leave the fastest on the grid. With `cache`
+        (a JSON file) a stored choice for this device, precision, grid and batch is applied
+        without timing, and a new search is stored. Returns (divisors, ms or None)."""
+        import json
+        import os
+        key = self.tile_key()
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                store = json.load(fh)
+            if key in store:
+                div = tuple(store[key]["div"])
+                self.set_line_tiles(div)
+                return div, None
+        if not any(self.line_tiles()[1]):
+            return self.line_tiles()[0], None
+        self.ensure_symbol()
+        assert phis.is_contiguous() and phis.dtype == self.cdtype
+        assert phis.numel() == self.batch * self.n[0] * self.n[1] * self.n[2]
+        if self.batch > 1 or not isinstance(params, bec_params):
+            params = (bec_params * self.batch)(*params)
+        div, ms = bec_autotune_line_tiles(self.handle, params, phis.data_ptr(), reps)
+        if log:
+            log(f"line tiles {key}: divisors {div}, {ms:.3f} ms per apply + Parseval pass")
+        if cache:
+            store[key] = dict(div=list(div), ms=ms)
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(store, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return div, ms
 
     def interp_to(self, dst: "BecGrid", phis, out_precision=BEC_FP64):
         """Spectral interpolation of `batch` fields on this grid to grid `dst` (same box).

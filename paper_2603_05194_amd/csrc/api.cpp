@@ -97,13 +97,20 @@ void hs_tiles(Geo& g) {
     g.ntiles = g.nreg + (g.nky + g.L - 1) / g.L;
 }
 
-Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
+// Lines per block of the runtime-length (generic LDS) line kernels: a tile of at most kTileElems
+// complex values (half that for two-field passes), divided by the grid's tile divisor for the axis.
+static int lines_per_block(int nfft, int dual, int div) {
+    int L = kTileElems / nfft;
+    if (dual) L /= 2;
+    L /= div;
+    return L < 1 ? 1 : L;
+}
+
+Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual, int div) {
     Geo g;
     std::memset(&g, 0, sizeof(g));
     g.axis = axis;
-    int L = kTileElems / nfft;
-    if (dual) L /= 2;
-    if (L < 1) L = 1;
+    int L = lines_per_block(nfft, dual, div);
     if (axis == 2) {
         g.n_outer = d0 * d1;
         g.n_inner = 1;
@@ -134,21 +141,18 @@ Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual) {
 }
 
 // Padded y passes over the half-spectrum buffers: lines along y at (x, kz), kz <= nz, rows of ld.
-Geo make_geo_hs_y(int nx, int nz, int nfft) {
-    Geo g = make_geo(1, nx, 0, nz + 1, nfft, 0);
+Geo make_geo_hs_y(int nx, int nz, int nfft, int div) {
+    Geo g = make_geo(1, nx, 0, nz + 1, nfft, 0, div);
     g.row = hs_ld(nz);
     return g;
 }
 
 // Padded x passes over [Nx][nky][ld]: columns (ky, kz), the Nyquist column kz = nz tiled apart.
-Geo make_geo_hs_x(int nky, int nz, int nfft, int dual) {
+Geo make_geo_hs_x(int nky, int nz, int nfft, int dual, int div) {
     Geo g;
     std::memset(&g, 0, sizeof(g));
     g.axis = 0;
-    int L = kTileElems / nfft;
-    if (dual) L /= 2;
-    if (L < 1) L = 1;
-    g.L = L;
+    g.L = lines_per_block(nfft, dual, div);
     g.n_outer = 1;
     g.n_inner = nky * (nz + 1);
     g.hs = 1;
@@ -158,6 +162,28 @@ Geo make_geo_hs_x(int nky, int nz, int nfft, int dual) {
     g.row = (long)nky * g.ld;
     hs_tiles(g);
     return g;
+}
+
+constexpr int kMaxTileDiv = 16;
+
+// Line-pass geometries from the grid size and the per-axis tile divisors. Only the generic
+// (runtime-length) kernels read L from here; the register kernels fix it per length.
+void plan_lines(Grid& g) {
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int* d = g.tile_div;
+    g.gz = make_geo(2, nx, ny, nz, nz, 0, d[2]);
+    g.gy = make_geo(1, nx, ny, nz, ny, 0, d[1]);
+    g.gx = make_geo(0, nx, ny, nz, nx, 0, d[0]);
+    g.g_ay = make_geo_hs_y(nx, nz, 2 * ny, d[1]);
+    g.g_ax = make_geo_hs_x(2 * ny, nz, 2 * nx, 0, d[0]);
+    g.g_ax2 = make_geo_hs_x(2 * ny, nz, 2 * nx, 1, d[0]);
+    g.zf_L = lines_per_block(2 * nz, 0, d[2]);
+}
+
+// Does axis a run any pass on the generic kernels (whose tiles the divisors set)?
+static bool axis_tunable(const Grid& g, int a) {
+    auto pow2 = [](int n) { return n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; };
+    return !g.use_rf || !pow2(g.n[a]) || !pow2(2 * g.n[a]);
 }
 
 Layout layout(const int n[3], int precision, int batch) {
@@ -519,13 +545,7 @@ int bec_init_grid_batched(const bec_grid_desc* desc, int precision, int batch, v
         carve_fields<float>(g->f32, p, g->n, batch);
     }
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
-    g->gz = make_geo(2, nx, ny, nz, nz, 0);
-    g->gy = make_geo(1, nx, ny, nz, ny, 0);
-    g->gx = make_geo(0, nx, ny, nz, nx, 0);
-    g->g_ay = make_geo_hs_y(nx, nz, 2 * ny);
-    g->g_ax = make_geo_hs_x(2 * ny, nz, 2 * nx, 0);
-    g->g_ax2 = make_geo_hs_x(2 * ny, nz, 2 * nx, 1);
-    g->zf_L = std::max(1, kTileElems / (2 * nz));
+    plan_lines(*g);
     const long N = (long)nx * ny * nz;
     g->bt64 = Bat{N, (long)nx * ny * hs_ld(nz), (long)nx * 2 * ny * hs_ld(nz), L.part_stride};
     g->bt32 = g->bt64;
@@ -753,6 +773,73 @@ int bec_time_stage(bec_grid g, const bec_params* pp, const void* d_phi, int whic
     else
         *avg_ms = time_stage<float>(*g, (const cpx<float>*)d_phi, which, reps);
     return check_launch(g, "time_stage");
+}
+
+int bec_set_line_tiles(bec_grid g, const int32_t div[3]) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!div) return fail(BEC_EINVAL, "div is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (div[a] < 1 || div[a] > kMaxTileDiv || (div[a] & (div[a] - 1)))
+            return fail(BEC_EINVAL, "tile divisors must be powers of two in [1, 16]");
+    for (int a = 0; a < 3; ++a) g->tile_div[a] = div[a];
+    plan_lines(*g);
+    return BEC_OK;
+}
+
+int bec_get_line_tiles(bec_grid g, int32_t div[3], int32_t tunable[3]) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!div) return fail(BEC_EINVAL, "div is NULL");
+    for (int a = 0; a < 3; ++a) {
+        div[a] = g->tile_div[a];
+        if (tunable) tunable[a] = axis_tunable(*g, a) ? 1 : 0;
+    }
+    return BEC_OK;
+}
+
+// Coordinate search over the per-axis divisors 1, 2, 4, ..., kMaxTileDiv (z, then y, then x):
+// each candidate is timed as one H apply plus one two-density Parseval pass (every line pass of
+// the iteration on every axis), `reps` times after one warm-up, with HIP events on the grid
+// stream. Axes whose passes all use the register kernels are skipped.
+int bec_autotune_line_tiles(bec_grid g, const bec_params* pp, const void* d_phi, int reps, int32_t div_out[3],
+                            double* ms_out) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_phi || reps < 1) return fail(BEC_EINVAL, "bad arguments");
+    if (!g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    if ((rc = upload_params(*g, pp))) return rc;
+    auto measure = [&]() {
+        if (g->precision == BEC_FP64)
+            return time_stage<double>(*g, (const cpx<double>*)d_phi, 2, reps) +
+                   time_stage<double>(*g, (const cpx<double>*)d_phi, 6, reps);
+        return time_stage<float>(*g, (const cpx<float>*)d_phi, 2, reps) +
+               time_stage<float>(*g, (const cpx<float>*)d_phi, 6, reps);
+    };
+    double best = measure();
+    if ((rc = check_launch(g, "autotune"))) return rc;
+    for (int a = 2; a >= 0; --a) {
+        if (!axis_tunable(*g, a)) continue;
+        const int keep = g->tile_div[a];
+        int pick = keep;
+        for (int d = 1; d <= kMaxTileDiv; d *= 2) {
+            if (d == keep) continue;
+            g->tile_div[a] = d;
+            plan_lines(*g);
+            const double t = measure();
+            if ((rc = check_launch(g, "autotune"))) return rc;
+            if (t < best) {
+                best = t;
+                pick = d;
+            }
+        }
+        g->tile_div[a] = pick;
+        plan_lines(*g);
+    }
+    if (div_out)
+        for (int a = 0; a < 3; ++a) div_out[a] = g->tile_div[a];
+    if (ms_out) *ms_out = best;
+    return BEC_OK;
 }
 
 }  // extern "C"

@@ -58,6 +58,7 @@ struct Grid {
     Geo gz, gy, gx;           // N grid line passes (z: Nz, y: Ny, x: Nx)
     Geo g_ay, g_ax, g_ax2;    // padded passes (y forward/inverse, x, two-field x)
     int zf_L;                 // packed lines per block of the runtime-length z pair kernels
+    int tile_div[3] = {1, 1, 1};   // per-axis divisor of the generic kernels' lines per block
     Bat bt64, bt32;           // per-solve strides of the FP64 / FP32 buffers
 };
 

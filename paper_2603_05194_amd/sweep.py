@@ -5,7 +5,7 @@ grid within a batch: one launch per phase serves all of its solves). The critica
 frequency for each dipolar strength is the first Omega at which the ground state carries a
 vortex, read as <L_z> = -E_rot / Omega >= 1/2 (Sec. 3, critical rotational frequency study).
 
-    python -m paper_2603_05194_amd.sweep [--quick] [--max-iter K] [--fp64]
+    python -m paper_2603_05194_amd.sweep [--quick] [--max-iter K] [--fp64] [--autotune [--tile-cache F]]
 """
 from __future__ import annotations
 
@@ -27,8 +27,10 @@ def group_by_grid(workloads):
     return groups
 
 
-def run_sweep(workloads, guesses, precision=BEC_FP32, opts=None, log=None):
+def run_sweep(workloads, guesses, precision=BEC_FP32, opts=None, log=None, autotune=False, tile_cache=None):
     """Solve every workload (batched per grid). `guesses[i]` is a complex128 numpy array.
+    With `autotune`, each grid's line tiles are searched (or read from `tile_cache`) on its
+    initial guesses first; the search time is reported apart (tune_seconds).
     Returns one dict per workload with status, iterations, energies and <L_z>."""
     import torch
     opts = opts or bec_pcg_default_opts()
@@ -39,6 +41,13 @@ def run_sweep(workloads, guesses, precision=BEC_FP32, opts=None, log=None):
         params = [make_params(workloads[i].gamma, workloads[i].beta, workloads[i].lam, workloads[i].ndip,
                               workloads[i].omega) for i in idx]
         phis = torch.from_numpy(np.stack([guesses[i] for i in idx])).to(g.device)
+        tune_s, tiles = 0.0, (1, 1, 1)
+        if autotune:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            tiles, _ = g.autotune(params, phis.to(g.cdtype), reps=3, cache=tile_cache, log=log)
+            tune_s = time.perf_counter() - t1
+            t0 += tune_s
         res = g.pcg_solve_batched(params, phis, opts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -47,7 +56,7 @@ def run_sweep(workloads, guesses, precision=BEC_FP32, opts=None, log=None):
             lz = -r.e.Erot / w.omega if w.omega != 0 else 0.0
             out[i] = dict(name=w.name, n=list(n), omega=w.omega, lam=w.lam, beta=w.beta, status=r.status,
                           iters=r.iters, fp32_iters=r.fp32_iters, res_inf=r.res_inf, E=r.e.E, mu=r.e.mu,
-                          Erot=r.e.Erot, Lz=lz, batch_seconds=dt)
+                          Erot=r.e.Erot, Lz=lz, batch_seconds=dt, tiles=list(tiles), tune_seconds=tune_s)
         if log:
             log(f"grid {n}: {len(idx)} solves in {dt:.1f}s, iterations {min(res[k].iters for k in range(len(idx)))}"
                 f"..{max(res[k].iters for k in range(len(idx)))}, converged "
@@ -80,6 +89,8 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true", help="quarter-size grids")
     ap.add_argument("--fp64", action="store_true", help="FP64 only (default: FP32 bulk + FP64 polish)")
     ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--autotune", action="store_true", help="search the line tiles of each grid first")
+    ap.add_argument("--tile-cache", default=None, help="JSON file of searched line tiles (read and written)")
     args = ap.parse_args(argv)
     import bec_inputs as bi
     ws = bi.batched_sweep(quick=args.quick)
@@ -88,7 +99,7 @@ def main(argv=None):
     o.max_iter = args.max_iter
     log = lambda s: print(s, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    res = run_sweep(ws, guesses, BEC_FP64 if args.fp64 else BEC_FP32, o, log)
+    res = run_sweep(ws, guesses, BEC_FP64 if args.fp64 else BEC_FP32, o, log, args.autotune, args.tile_cache)
     total = time.perf_counter() - t0
     oc = critical_omega(res)
     print(json.dumps({"seconds": total, "solves": len(res), "converged": sum(r["status"] == 0 for r in res),
