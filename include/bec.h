@@ -192,8 +192,9 @@ int bec_rotate_z(bec_grid g, const void* d_in, void* d_out, double alpha);
  * Synchronises. */
 int bec_time_stage(bec_grid g, const bec_params* p, const void* d_phi, int which, int reps, double* avg_ms);
 
-/* Line tiles of the runtime-length FFT kernels (lengths other than 32..1024 powers of two, or
- * every length when the register kernels are switched off). These kernels hold one tile of at
+/* Line tiles of the runtime-length FFT kernels: lengths without register kernels (those have
+ * 32..1024 powers of two and 48, 96, 192, 384, 160, 320), or every length when the register
+ * kernels are switched off. These kernels hold one tile of at
  * most 4096 complex values per block, 2048 for two-field passes. div[a] (a = 0: x, 1: y, 2: z)
  * divides the number of lines per block of every pass along axis a, padded passes included.
  * div[a] must be a power of two in [1, 16]; the default is 1. Tiles change the partition of the

@@ -182,8 +182,7 @@ void plan_lines(Grid& g) {
 
 // Does axis a run any pass on the generic kernels (whose tiles the divisors set)?
 static bool axis_tunable(const Grid& g, int a) {
-    auto pow2 = [](int n) { return n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; };
-    return !g.use_rf || !pow2(g.n[a]) || !pow2(2 * g.n[a]);
+    return !g.use_rf || !rf_length(g.n[a]) || !rf_length(2 * g.n[a]);
 }
 
 Layout layout(const int n[3], int precision, int batch) {

@@ -29,6 +29,16 @@ constexpr int kMaxStages = 12;
 constexpr int kMaxRed = 32;           // reduction slots per kernel
 constexpr int kRedBlocks = 1024;      // blocks of the grid-stride pointwise reductions
 
+// Line lengths with register-resident FFT kernels: powers of two 32..1024 and 3 or 5 times a
+// power of two (48..384, 160, 320). Every other length runs on the runtime-length LDS kernels.
+__host__ __device__ inline bool rf_length(int n) {
+    switch (n) {
+        case 32: case 64: case 128: case 256: case 512: case 1024:
+        case 48: case 96: case 192: case 384: case 160: case 320: return true;
+        default: return false;
+    }
+}
+
 // Per-size FFT plan (device-visible, passed by value).
 struct FftPlan {
     int n;

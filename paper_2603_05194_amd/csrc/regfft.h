@@ -1,11 +1,14 @@
-// Register-resident batched FFT for power-of-two line lengths known at compile time.
+// Register-resident batched FFT for line lengths known at compile time: powers of two, and
+// c 2^p with c = 3 or 5.
 //
 // A block of 256 threads transforms L lines of N points; each thread keeps E points of one
-// line in registers. Stage s of radix R_s (radix 2 or 4 first when log2 N is not a multiple of
-// 3, then radix 8) applies the Stockham step
+// line in registers. Stage s of radix R_s applies the Stockham step
 //   v_k = x[j + k N/R] * w^(k (j mod Ns)),  v = DFT_R(v),  y[(j - j mod Ns) R + j mod Ns + k Ns] = v_k
 // to the E/R butterflies j = jb + (N/E) b of the thread; between stages the points go through
-// LDS once (write outputs, barrier, read the next stage's inputs, barrier).
+// LDS once (write outputs, barrier, read the next stage's inputs, barrier). Radices, forward
+// order: for N = 2^p, radix 2 or 4 first when p is not a multiple of 3, then radix 8; for
+// N = c 2^p, radix c, then radix 2 when p is odd, then radix 4, so that E = 4c points per
+// thread is a multiple of every radix and N / E stays a power of two.
 //
 // Register layouts: on entry v[b R_first + k] = x[jb + (N/E) b + k N/R_first]; on exit
 // v[b R_last + k] = X[jb + (N/E) b + k N/R_last] (natural-order frequency index). The inverse
@@ -20,12 +23,18 @@ namespace bec {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-template <int N> struct Pow2Plan {
-    static constexpr int p = ilog2(N);
-    static constexpr int rem = p % 3;
-    static constexpr int ns = p / 3 + (rem ? 1 : 0);
-    // forward order: the small radix first
-    static constexpr int fwd(int s) { return (rem && s == 0) ? (1 << rem) : 8; }
+constexpr int odd_part(int n) { return n % 2 ? n : odd_part(n / 2); }
+
+template <int N> struct RfPlan {
+    static constexpr int c = odd_part(N);         // 1, 3 or 5
+    static constexpr int p = ilog2(N / c);
+    static_assert(c == 1 || c == 3 || c == 5, "register FFT lengths are 2^p, 3 2^p or 5 2^p");
+    static constexpr int rem = c == 1 ? p % 3 : p % 2;
+    static constexpr int ns = c == 1 ? p / 3 + (rem ? 1 : 0) : 1 + p / 2 + rem;
+    // forward order: the odd radix, then the small power-of-two radix, then the large ones
+    static constexpr int fwd(int s) {
+        return c == 1 ? ((rem && s == 0) ? (1 << rem) : 8) : (s == 0 ? c : ((rem && s == 1) ? 2 : 4));
+    }
     static constexpr int inv(int s) { return fwd(ns - 1 - s); }
     template <int DIR> static constexpr int radix(int s) { return DIR < 0 ? fwd(s) : inv(s); }
     template <int DIR> static constexpr int span(int s) {   // product of the radices before s
@@ -33,8 +42,10 @@ template <int N> struct Pow2Plan {
     }
 };
 
-// points per thread: enough lines per block for 128-byte column segments, at least 8
+// points per thread. Powers of two: enough lines per block for 128-byte column segments, at
+// least 8. c 2^p: 4c, the least multiple of every radix of the plan.
 template <typename R> constexpr int rf_points(int N) {
+    if (odd_part(N) > 1) return 4 * odd_part(N);
     const int per_seg = 128 / (int)sizeof(cpx<R>);          // complex values per 128 B
     int e = per_seg * N / kThreads;
     if (e < 8) e = 8;
@@ -53,7 +64,7 @@ template <typename R, int N, int E> struct RF {
 template <typename R, int N, int E, int DIR, int S>
 __device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line, int jb,
                                        const cpx<R>* __restrict__ tw) {
-    using P = Pow2Plan<N>;
+    using P = RfPlan<N>;
     constexpr int RD = P::template radix<DIR>(S);
     constexpr int Ns = P::template span<DIR>(S);
     constexpr int TPL = N / E;
@@ -65,14 +76,14 @@ __device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line
         if constexpr (Ns > 1) {
             // one table read per butterfly; the other twiddles are its powers (at most three
             // products deep: w2 = w1 w1, w3 = w2 w1, w4 = w2 w2, w5 = w4 w1, w6 = w3 w3, w7 = w4 w3)
-            const int jm = j & (Ns - 1);
+            const int jm = j % Ns;
             cpx<R> w[RD];
             w[1] = tw[jm * (N / (Ns * RD))];
             if constexpr (DIR > 0) w[1] = conj(w[1]);
             if constexpr (RD > 2) w[2] = cmul(w[1], w[1]);
             if constexpr (RD > 3) w[3] = cmul(w[2], w[1]);
-            if constexpr (RD > 4) {
-                w[4] = cmul(w[2], w[2]);
+            if constexpr (RD > 4) w[4] = cmul(w[2], w[2]);
+            if constexpr (RD > 5) {
                 w[5] = cmul(w[4], w[1]);
                 w[6] = cmul(w[3], w[3]);
                 w[7] = cmul(w[4], w[3]);
@@ -88,7 +99,7 @@ __device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line
 #pragma unroll
         for (int b = 0; b < BPT; ++b) {
             const int j = jb + TPL * b;
-            const int jm = j & (Ns - 1);
+            const int jm = j % Ns;
             cpx<R>* o = line + (j - jm) * RD + jm;
 #pragma unroll
             for (int k = 0; k < RD; ++k) o[k * Ns] = v[b * RD + k];
@@ -114,14 +125,14 @@ __device__ __forceinline__ void rf_fft(cpx<R> (&v)[E], cpx<R>* line, int jb, con
 // Index (within the line) of register slot i for the entry layout of direction DIR
 // (i.e. the layout rf_fft<DIR> expects on entry).
 template <int N, int E, int DIR> __device__ __forceinline__ int rf_in_index(int jb, int i) {
-    using P = Pow2Plan<N>;
+    using P = RfPlan<N>;
     constexpr int RD = P::template radix<DIR>(0);
     return jb + (N / E) * (i / RD) + (i % RD) * (N / RD);
 }
 
 // Index of register slot i for the exit layout of direction DIR.
 template <int N, int E, int DIR> __device__ __forceinline__ int rf_out_index(int jb, int i) {
-    using P = Pow2Plan<N>;
+    using P = RfPlan<N>;
     constexpr int RD = P::template radix<DIR>(P::ns - 1);
     return jb + (N / E) * (i / RD) + (i % RD) * (N / RD);
 }

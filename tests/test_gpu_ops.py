@@ -114,3 +114,43 @@ def test_generic_and_power_of_two_paths_agree(name, n, monkeypatch):
     assert rel_max(out[0][0], out[1][0]) < 1e-13
     for k in ("E", "mu", "Edip"):
         assert abs(out[0][1][k] - out[1][1][k]) < 1e-13 * abs(out[1][1][k]) + 1e-15
+
+
+MIXED_RADIX = [(96, 48, 160), (192, 20, 48), (160, 8, 96), (48, 16, 16)]
+
+
+@pytest.mark.parametrize("n", MIXED_RADIX)
+def test_mixed_radix_register_fft_matches_numpy(n):
+    """Register kernels for 3 2^p and 5 2^p lengths (radix-3/5 stage, then radix 2 and 4)."""
+    g = bec.BecGrid(n, (1.0, 1.0, 1.0))
+    rng = np.random.default_rng(12)
+    u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    print(f"fft3d {n}", flush=True)
+    assert rel_max(host(g.fft3d(dev(u), -1)), np.fft.fftn(u)) < 1e-14 * math.log2(np.prod(n))
+    assert rel_max(host(g.fft3d(dev(u), +1)), np.fft.ifftn(u) * np.prod(n)) < 1e-14 * math.log2(np.prod(n))
+
+
+@pytest.mark.parametrize("n", [(96, 48, 160), (192, 160, 8)])
+def test_mixed_radix_apply_H_matches_oracle_and_generic(n, monkeypatch):
+    """H phi on grids whose N-grid and padded lengths (2N) are all 3 2^p or 5 2^p: register and
+    runtime-length kernels agree, both match the oracle, in FP64; FP32 within its rounding."""
+    a = (6.0, 4.0, 5.0)
+    m = Model(n, a, (1.0, 1.4, 0.8), 60.0, -30.0, (0.6, 0.0, 0.8), 0.5)
+    rng = np.random.default_rng(7)
+    X, Y, Z = Grid(n, a).mesh()
+    env = np.exp(-0.5 * (X ** 2 + 1.4 * Y ** 2 + 0.8 * Z ** 2))
+    phi = bi.normalize(env * (1 + 0.1 * rng.standard_normal(n)) * np.exp(0.3j * rng.standard_normal(n)), n, a)
+    ref = m.H(phi)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BEC_GENERIC_FFT", flag)
+        g = bec.BecGrid(n, a)
+        print(f"apply_H {n} generic={flag}", flush=True)
+        h, mu = g.apply_H(params_of(m), dev(phi))
+        out.append(host(h))
+        assert rel_max(out[-1], ref) < 1e-12
+    assert rel_max(out[0], out[1]) < 1e-13
+    monkeypatch.setenv("BEC_GENERIC_FFT", "0")
+    g32 = bec.BecGrid(n, a, precision=bec.BEC_FP32)
+    h32, _ = g32.apply_H(params_of(m), dev(phi.astype(np.complex64)))
+    assert rel_max(host(h32), ref) < 2e-5
