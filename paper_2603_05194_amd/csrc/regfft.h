@@ -16,6 +16,8 @@
 // layout ends in the forward's entry layout: forward -> pointwise multiply -> inverse needs no
 // extra data movement.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "fft.h"
 
@@ -59,10 +61,16 @@ template <typename R, int N, int E> struct RF {
     static constexpr int L = kThreads / TPL;   // lines per block
     static constexpr int LD = N + 1;           // LDS line stride (odd: spreads banks)
     static constexpr size_t lds_bytes = (size_t)L * LD * sizeof(cpx<R>);
+    // Line kernels whose complex tile exceeds 48 KB exchange one component at a time through a
+    // real tile of half the size (two barriers more per stage), so that LDS admits twice the
+    // blocks per CU (FP64 N = 512: 64 KB -> 32 KB, four blocks instead of two).
+    static constexpr bool SPLIT = lds_bytes > 48 * 1024;
+    static constexpr size_t lds_line_bytes = SPLIT ? (size_t)L * LD * sizeof(R) : lds_bytes;
 };
 
-template <typename R, int N, int E, int DIR, int S>
-__device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line, int jb,
+// LP is the LDS element type: cpx<R> (whole complex values) or R (one component at a time).
+template <typename R, int N, int E, int DIR, int S, typename LP>
+__device__ __forceinline__ void rf_run(cpx<R> (&v)[E], LP* __restrict__ line, int jb,
                                        const cpx<R>* __restrict__ tw) {
     using P = RfPlan<N>;
     constexpr int RD = P::template radix<DIR>(S);
@@ -96,30 +104,57 @@ __device__ __forceinline__ void rf_run(cpx<R> (&v)[E], cpx<R>* __restrict__ line
     if constexpr (S + 1 < P::ns) {
         constexpr int RN = P::template radix<DIR>(S + 1);
         constexpr int BN = E / RN;
+        if constexpr (sizeof(LP) == sizeof(cpx<R>)) {
 #pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = jb + TPL * b;
-            const int jm = j % Ns;
-            cpx<R>* o = line + (j - jm) * RD + jm;
+            for (int b = 0; b < BPT; ++b) {
+                const int j = jb + TPL * b;
+                const int jm = j % Ns;
+                LP* o = line + (j - jm) * RD + jm;
 #pragma unroll
-            for (int k = 0; k < RD; ++k) o[k * Ns] = v[b * RD + k];
+                for (int k = 0; k < RD; ++k) o[k * Ns] = v[b * RD + k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < BN; ++b) {
+                const int j = jb + TPL * b;
+#pragma unroll
+                for (int k = 0; k < RN; ++k) v[b * RN + k] = line[j + k * (N / RN)];
+            }
+            __syncthreads();
+        } else {
+            // real parts out, new real parts in, then the same for the imaginary parts: the
+            // imaginary registers still hold the old layout while the real ones are exchanged
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int b = 0; b < BPT; ++b) {
+                    const int j = jb + TPL * b;
+                    const int jm = j % Ns;
+                    LP* o = line + (j - jm) * RD + jm;
+#pragma unroll
+                    for (int k = 0; k < RD; ++k) o[k * Ns] = c ? v[b * RD + k].y : v[b * RD + k].x;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int b = 0; b < BN; ++b) {
+                    const int j = jb + TPL * b;
+#pragma unroll
+                    for (int k = 0; k < RN; ++k) {
+                        if (c) v[b * RN + k].y = line[j + k * (N / RN)];
+                        else v[b * RN + k].x = line[j + k * (N / RN)];
+                    }
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
-#pragma unroll
-        for (int b = 0; b < BN; ++b) {
-            const int j = jb + TPL * b;
-#pragma unroll
-            for (int k = 0; k < RN; ++k) v[b * RN + k] = line[j + k * (N / RN)];
-        }
-        __syncthreads();
         rf_run<R, N, E, DIR, S + 1>(v, line, jb, tw);
     }
 }
 
-// Full transform; `line` is this thread's line in LDS (lds + l * LD).
-template <typename R, int N, int E, int DIR>
-__device__ __forceinline__ void rf_fft(cpx<R> (&v)[E], cpx<R>* line, int jb, const cpx<R>* tw) {
-    rf_run<R, N, E, DIR, 0>(v, line, jb, tw);
+// Full transform; `line` is this thread's line in LDS (lds + l * LD elements of type LP).
+template <typename R, int N, int E, int DIR, typename LP>
+__device__ __forceinline__ void rf_fft(cpx<R> (&v)[E], LP* line, int jb, const cpx<R>* tw) {
+    rf_run<R, N, E, DIR, 0, LP>(v, line, jb, tw);
 }
 
 // Index (within the line) of register slot i for the entry layout of direction DIR
