@@ -101,15 +101,6 @@ template <typename R, int N> struct RFK {
     static constexpr int L = T::L;
 };
 
-// The two-density Parseval pass keeps two spectra in registers: half the points per thread of
-// the line kernels for power-of-two lengths (at least 8), so that its registers and LDS tile
-// admit as many waves as the one-field passes (column segments of 64 bytes at FP64 N = 512).
-template <typename R, int N> struct RFK2 {
-    static constexpr int E = odd_part(N) > 1 ? rf_points<R>(N) : (rf_points<R>(N) / 2 < 8 ? 8 : rf_points<R>(N) / 2);
-    using T = RF<R, N, E>;
-    static constexpr int L = T::L;
-};
-
 #include "ops.inc"
 #include "special.inc"
 
