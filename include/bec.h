@@ -188,9 +188,10 @@ int bec_rotate_z(bec_grid g, const void* d_in, void* d_out, double alpha);
  * padded x pass (forward, symbol multiply, inverse); 1: the whole ATKM potential of |phi|^2;
  * 2: the whole H phi apply; 3: the 3-D FFT of phi (forward); 4: a plain copy of one complex
  * field (bandwidth calibration); 5: the ATKM padded y forward pass; 6: the two-density
- * padded x Parseval pass of the step model. 0 and 5 alternate between the grid's two ATKM
- * buffer pairs from run to run, so that a run does not find its input in the last-level cache
- * left by the previous one. Needs bec_atkm_symbol except for 3 and 4. Synchronises. */
+ * padded x Parseval pass of the step model. 0, 5 and 6 are timed as inside the iteration:
+ * before each run the kernels that produce the pass's input run again, untimed, and the pass
+ * kernel is launched with start and stop events of its own, so the mean is the kernel's
+ * duration. Needs bec_atkm_symbol except for 3 and 4. Synchronises. */
 int bec_time_stage(bec_grid g, const bec_params* p, const void* d_phi, int which, int reps, double* avg_ms);
 
 /* Line tiles of the runtime-length FFT kernels: lengths without register kernels (those have

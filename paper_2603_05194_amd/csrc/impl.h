@@ -59,6 +59,9 @@ struct Grid {
     Geo g_ay, g_ax, g_ax2;    // padded passes (y forward/inverse, x, two-field x)
     int zf_L;                 // packed lines per block of the runtime-length z pair kernels
     int tile_div[3] = {1, 1, 1};   // per-axis divisor of the generic kernels' lines per block
+    // when set, the next line pass (or two-density Parseval pass) is launched with these events
+    // recording its own start and end (stage timing)
+    hipEvent_t tev0 = nullptr, tev1 = nullptr;
     Bat bt64, bt32;           // per-solve strides of the FP64 / FP32 buffers
 };
 
