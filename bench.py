@@ -45,9 +45,9 @@ def pass_bytes(which, n, csize):
 # calibration; see the hbm_traffic summary under profiles/), valid while the kernel sources
 # hash to `src`.
 MEASURED_TRAFFIC = {
-    "y_fwd": {"bytes": 214.1e6, "src": "5ab100818956b8a4"},
-    "x_pass": {"bytes": 354.7e6, "src": "5ab100818956b8a4"},
-    "x_pars2": {"bytes": 367.8e6, "src": "5ab100818956b8a4"},
+    "y_fwd": {"bytes": 214.1e6, "src": "74403aa330b3f8fb"},
+    "x_pass": {"bytes": 355.5e6, "src": "74403aa330b3f8fb"},
+    "x_pars2": {"bytes": 367.7e6, "src": "74403aa330b3f8fb"},
 }
 
 
