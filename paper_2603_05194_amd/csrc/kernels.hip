@@ -99,6 +99,20 @@ template <typename R, int N> struct RFK {
     static constexpr int E = rf_points<R>(N);
     using T = RF<R, N, E>;
     static constexpr int L = T::L;
+    static constexpr int NT = kThreads;
+};
+
+// Two-density Parseval pass: both spectra live in registers. For power-of-two lengths with at
+// least 16 points per thread it takes half of them in blocks of twice the threads: the same L
+// lines per block (128-byte column segments, the same tiles and partial rows as RFK) with
+// registers low enough for four waves per SIMD.
+template <typename R, int N> struct RFK2 {
+    static constexpr int E1 = rf_points<R>(N);
+    static constexpr int E = (odd_part(N) > 1 || E1 < 16) ? E1 : E1 / 2;
+    static constexpr int NT = kThreads * (E1 / E);
+    using T = RF<R, N, E, NT>;
+    static constexpr int L = T::L;
+    static_assert(L == RFK<R, N>::L, "same tiles as the line kernels");
 };
 
 #include "ops.inc"

@@ -103,11 +103,11 @@ __device__ __forceinline__ void visit_lds(cpx<R>* lds, int ldl, int L, int n, F 
     }
 }
 
-// Block reduction of NQ doubles; slot q is a max-reduction if bit q of MAXMASK is set.
-// Writes partials[blockIdx.x * NQ + q].
-template <int NQ, unsigned MAXMASK>
+// Block reduction of NQ doubles over NT threads; slot q is a max-reduction if bit q of MAXMASK
+// is set. Writes partials[blockIdx.x * NQ + q].
+template <int NQ, unsigned MAXMASK, int NT = kThreads>
 __device__ __forceinline__ void block_reduce(double (&v)[NQ], double* __restrict__ partials) {
-    __shared__ double red[kThreads / 64][NQ > 0 ? NQ : 1];
+    __shared__ double red[NT / 64][NQ > 0 ? NQ : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -124,7 +124,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ], double* __restrict
     if (threadIdx.x < NQ) {
         const int q = threadIdx.x;
         double x = red[0][q];
-        for (int w = 1; w < kThreads / 64; ++w) x = ((MAXMASK >> q) & 1u) ? fmax(x, red[w][q]) : x + red[w][q];
+        for (int w = 1; w < NT / 64; ++w) x = ((MAXMASK >> q) & 1u) ? fmax(x, red[w][q]) : x + red[w][q];
         partials[(long)blockIdx.x * NQ + q] = x;
     }
 }

@@ -56,9 +56,9 @@ template <typename R> constexpr int rf_points(int N) {
     return e;
 }
 
-template <typename R, int N, int E> struct RF {
+template <typename R, int N, int E, int NT = kThreads> struct RF {
     static constexpr int TPL = N / E;          // threads per line
-    static constexpr int L = kThreads / TPL;   // lines per block
+    static constexpr int L = NT / TPL;         // lines per block of NT threads
     static constexpr int LD = N + 1;           // LDS line stride (odd: spreads banks)
     static constexpr size_t lds_bytes = (size_t)L * LD * sizeof(cpx<R>);
     // Line kernels whose complex tile exceeds 48 KB exchange one component at a time through a
