@@ -45,9 +45,9 @@ def pass_bytes(which, n, csize):
 # calibration; see the hbm_traffic summary under profiles/), valid while the kernel sources
 # hash to `src`.
 MEASURED_TRAFFIC = {
-    "y_fwd": {"bytes": 214.1e6, "src": "74403aa330b3f8fb"},
-    "x_pass": {"bytes": 355.5e6, "src": "74403aa330b3f8fb"},
-    "x_pars2": {"bytes": 367.7e6, "src": "74403aa330b3f8fb"},
+    "y_fwd": {"bytes": 214.1e6, "src": "c90709a1e1a09feb"},
+    "x_pass": {"bytes": 355.4e6, "src": "c90709a1e1a09feb"},
+    "x_pars2": {"bytes": 367.6e6, "src": "c90709a1e1a09feb"},
 }
 
 
