@@ -826,7 +826,11 @@ int bec_autotune_line_tiles(bec_grid g, const bec_params* pp, const void* d_phi,
             g->tile_div[a] = d;
             plan_lines(*g);
             const double t = measure();
-            if ((rc = check_launch(g, "autotune"))) return rc;
+            if ((rc = check_launch(g, "autotune"))) {
+                g->tile_div[a] = pick;   // leave the best set found so far
+                plan_lines(*g);
+                return rc;
+            }
             if (t < best) {
                 best = t;
                 pick = d;
