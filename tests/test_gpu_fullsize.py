@@ -1,7 +1,8 @@
-"""Parity at the full pancake size (256 x 256 x 64, padded 512 x 512 x 128): the kernels and
-launch shapes the bench times, against the oracle on the whole grid (the oracle's symbol comes
-from its octant form, a few seconds on the host). Symbol, ATKM potential, H phi, mu and the energy
-parts, the first PCG iterations (Algorithm 1) in FP64, and H phi in FP32."""
+"""Parity at full size against the oracle on the whole grid (the oracle's symbol comes from its
+octant form, a few seconds on the host). For the pancake, 256 x 256 x 64 (padded 512 x 512 x 128),
+in the kernels and launch shapes the bench times: the symbol, the ATKM potential, H phi, mu and
+the energy parts, the first PCG iterations (Algorithm 1) in FP64, and H phi in FP32. For the
+cigar, 128 x 128 x 256: H phi and the energies in FP64 and H phi in FP32."""
 import numpy as np
 import pytest
 
@@ -75,3 +76,23 @@ def test_apply_H_fp32_full_size(full):
     g = bec.BecGrid(W.n, W.a, precision=bec.BEC_FP32)
     h, _ = g.apply_H(params_of(m), dev(phi0.astype(np.complex64)))
     assert rel_max(host(h), m.H(phi0)) < 2e-5
+
+
+def test_cigar_full_size_apply_and_energy():
+    torch_mod()
+    w = bi.WORKLOADS["cigar_128"]
+    print("oracle model at 128x128x256", flush=True)
+    m = Model.from_workload(w, uhat_full=osym.symbol_full_by_octant(Grid(w.n, w.a)))
+    phi0 = bi.initial_guess(w)
+    ref = m.H(phi0)
+    g = bec.BecGrid(w.n, w.a)
+    h, mu = g.apply_H(params_of(m), dev(phi0))
+    assert rel_max(host(h), ref) < 1e-12
+    e = m.energies(phi0).as_dict()
+    got = g.energy(params_of(m), dev(phi0))
+    scale = sum(abs(e[k]) for k in ("Ekin", "Epot", "Eint", "Edip", "Erot"))
+    for k in ("E", "Ekin", "Epot", "Eint", "Edip", "Erot", "mu"):
+        assert abs(got[k] - e[k]) < 1e-12 * scale, (k, got[k], e[k])
+    g32 = bec.BecGrid(w.n, w.a, precision=bec.BEC_FP32)
+    h32, _ = g32.apply_H(params_of(m), dev(phi0.astype(np.complex64)))
+    assert rel_max(host(h32), ref) < 2e-5
