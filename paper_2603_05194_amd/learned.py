@@ -308,6 +308,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--time-step", type=int, default=0, metavar="B",
                     help="only time training steps at batch B on a synthetic batch and exit")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="skip training: evaluate the shipped network on the held-out draws at --eval-grid")
     ap.add_argument("--train", type=int, default=2000, help="training draws (seeds 0..)")
     ap.add_argument("--val", type=int, default=64, help="held-out draws (seeds 10^6..)")
     ap.add_argument("--max-iter", type=int, default=4000)
@@ -321,6 +323,14 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.time_step:
         print(json.dumps(time_step(args.time_step)), flush=True)
+        return
+    if args.eval_only:
+        grid = tuple(args.eval_grid or (256, 256, 64))
+        log = lambda s: print(s, file=sys.stderr, flush=True)
+        val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(args.val)]
+        rows = evaluate(load_default(), val, grid, max_iter=args.max_iter, log=log)
+        print(json.dumps(dict(eval=dict(grid=list(grid), max_iter=args.max_iter, summary=summarize(rows),
+                                        rows=rows))), flush=True)
         return
     log = lambda s: print(s, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
