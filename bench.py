@@ -2,11 +2,13 @@
 on one MI355X), with H phi throughput, PCG iteration rate, the dominant kernel's HBM roofline
 fraction, the mixed-precision path and the CPU oracle baseline on the host cores.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-learned] [--no-mg] [--quick]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-learned] [--with-mg] [--with-mixed]
+                [--quick]
 A step is one full FP64 solve (||H phi - mu phi||_inf <= 1e-8) from a seeded random-phase guess;
 inputs are resident in HBM before the timed region. The same line reports the same workload
 solved from the learned guess (FP32 bulk + FP64 polish; network and interpolation inside the
-timed region) and by the three-level cascadic multigrid of Algorithm 2. Prints one JSON line.
+timed region) and, with --with-mg, by the three-level cascadic multigrid of Algorithm 2 (about
+2.5 more minutes of GPU time). Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -110,7 +112,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--with-mixed", action="store_true", help="also time mixed precision from the plain guess")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-mg", action="store_true")
+    ap.add_argument("--with-mg", action="store_true", help="also time the cascadic multigrid (Algorithm 2)")
+    ap.add_argument("--no-mg", action="store_true", help="(the default; kept for older command lines)")
     ap.add_argument("--quick", action="store_true", help="reduced grid (for testing the script)")
     ap.add_argument("--max-iter", type=int, default=None,
                     help="cap PCG iterations (profiling runs only; the result is then not a ground state)")
@@ -214,7 +217,7 @@ def main():
     # Algorithm 2 (cascadic multigrid, three levels N/4 -> N/2 -> N), FP32 bulk + FP64 polish on
     # each level, from the same random-phase guess generated on the coarsest grid.
     mg = None
-    if not args.no_mg:
+    if args.with_mg and not args.no_mg:
         from paper_2603_05194_amd import multigrid as MG
         nl0 = MG.levels(n)[0]
         phi0 = torch.from_numpy(bi.initial_guess(bi.Workload(**{**w.to_dict(), "seed": 0}), nl0)).to(dev)
