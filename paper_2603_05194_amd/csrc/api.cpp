@@ -141,9 +141,16 @@ Geo make_geo(int axis, int d0, int d1, int d2, int nfft, int dual, int div) {
 }
 
 // Padded y passes over the half-spectrum buffers: lines along y at (x, kz), kz <= nz, rows of ld.
+// The Nyquist column kz = nz is tiled apart (L rows x per tile), as in the x passes, instead of
+// filling one lane of a ninth L-column tile per x.
 Geo make_geo_hs_y(int nx, int nz, int nfft, int div) {
     Geo g = make_geo(1, nx, 0, nz + 1, nfft, 0, div);
     g.row = hs_ld(nz);
+    g.hs = 1;
+    g.nky = nx;   // the tiled count (rows x)
+    g.nzq = nz;
+    g.ld = hs_ld(nz);
+    hs_tiles(g);
     return g;
 }
 

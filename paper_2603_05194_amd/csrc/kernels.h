@@ -17,7 +17,8 @@ struct Geo {
     int dA, dB;       // axis 2: dA = d1 (to split outer); axis 0: dB = d2 (to split inner)
     long row;         // axes 0/1: elements between consecutive points of a line
     // axis 0 over a half-spectrum buffer [Nx][nky][ld] (hs = 1): tiles of L columns ky at the
-    // Nyquist kz = nzq, then tiles of L columns kz < nzq at one ky (cpk per ky, nreg in all)
+    // Nyquist kz = nzq, then tiles of L columns kz < nzq at one ky (cpk per ky, nreg in all).
+    // axis 1 over [Nx][ny][ld] (hs = 1): the same with rows x in place of columns ky (nky = Nx).
     int hs, nky, nzq, ld, cpk, nreg;
 };
 
