@@ -312,6 +312,7 @@ def main(argv=None):
                     help="skip training: evaluate the shipped network on the held-out draws at --eval-grid")
     ap.add_argument("--train", type=int, default=2000, help="training draws (seeds 0..)")
     ap.add_argument("--val", type=int, default=64, help="held-out draws (seeds 10^6..)")
+    ap.add_argument("--val-start", type=int, default=0, help="first held-out seed offset (--eval-only)")
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--epochs", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=64)
@@ -327,7 +328,7 @@ def main(argv=None):
     if args.eval_only:
         grid = tuple(args.eval_grid or (256, 256, 64))
         log = lambda s: print(s, file=sys.stderr, flush=True)
-        val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(args.val)]
+        val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(args.val_start, args.val_start + args.val)]
         rows = evaluate(load_default(), val, grid, max_iter=args.max_iter, log=log)
         print(json.dumps(dict(eval=dict(grid=list(grid), max_iter=args.max_iter, summary=summarize(rows),
                                         rows=rows))), flush=True)
