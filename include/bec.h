@@ -75,13 +75,15 @@ typedef struct {
     int32_t max_halvings;  /* step halvings before a forced accept (default 30)               */
     double t_default;      /* step when the quadratic model is not convex (default 0.3)       */
     double tau_E_ulps;     /* energy-test slack in ulps of sum |E parts| (default 64)         */
-    double switch_res;     /* mixed precision: FP32 -> FP64 when ||r||_inf <= this (1e-5)     */
+    double switch_res;     /* mixed precision: FP32 -> FP64 when ||r||_inf <= this (1e-5),    */
+                           /* times |mu| when switch_relative is set                          */
     int32_t check_every;   /* host polls the device state every k iterations (default 16)     */
     int32_t debug_flags;   /* bit0: force first trial step debug_t; bit1: force c2 = debug_c2 */
     double debug_t;
     double debug_c2;
     int32_t stall_window;  /* mixed: switch to FP64 if ||r||_inf has not improved this long   */
     int32_t use_graph;     /* 1: replay iterations from a captured HIP graph (default 1)     */
+    int32_t switch_relative; /* 1 (default): the FP32 -> FP64 switch is ||r||_inf <= switch_res |mu| */
 } bec_pcg_opts;
 
 typedef struct {
@@ -193,6 +195,39 @@ int bec_rotate_z(bec_grid g, const void* d_in, void* d_out, double alpha);
  * kernel is launched with start and stop events of its own, so the mean is the kernel's
  * duration. Needs bec_atkm_symbol except for 3 and 4. Synchronises. */
 int bec_time_stage(bec_grid g, const bec_params* p, const void* d_phi, int which, int reps, double* avg_ms);
+
+/* Launch sites of one iteration of Algorithm 1, as reported by bec_pcg_profile. */
+enum {
+    BEC_SITE_CONTROL = 0,  /* single-thread control kernels and the energy finish of the apply   */
+    BEC_SITE_FINISH,       /* ordered finishes of the FP64 block partial sums                     */
+    BEC_SITE_PREC_Z,       /* r = H phi - mu phi, ||r||_inf, sqrt(P_V) r, forward z transform     */
+    BEC_SITE_PREC_Y,       /* preconditioner y forward and inverse transforms (2 launches)       */
+    BEC_SITE_PREC_X,       /* preconditioner x: forward, division by alpha + |nu|^2/2, inverse    */
+    BEC_SITE_PREC_ZI,      /* inverse z, times sqrt(P_V) -> P r, direction inner products         */
+    BEC_SITE_DIR_Z,        /* direction update p, z R2C of Re(conj(phi) p) and |p|^2, step sums  */
+    BEC_SITE_Y_FWD,        /* ATKM padded y forward (2 for the step model, 1 in the apply)        */
+    BEC_SITE_X_PARS2,      /* two-density padded x Parseval pass of the step model               */
+    BEC_SITE_P_LINES,      /* kinetic and rotation Parseval sums of p along z, y, x (3 launches) */
+    BEC_SITE_RETRACT,      /* retraction phi <- cos(t||p||) phi + sin(t||p||) p / ||p||           */
+    BEC_SITE_ATKM_Z,       /* ATKM z R2C of |phi|^2 (pairs of real lines)                         */
+    BEC_SITE_X_ATKM,       /* ATKM padded x pass: forward, symbol multiply, inverse              */
+    BEC_SITE_Y_INV,        /* ATKM padded y inverse and crop                                      */
+    BEC_SITE_ATKM_ZI,      /* ATKM z C2R and crop -> Phi                                          */
+    BEC_SITE_H_Z,          /* kinetic line operator along z                                       */
+    BEC_SITE_H_Y,          /* kinetic + rotation line operator along y                            */
+    BEC_SITE_H_X,          /* kinetic + rotation line operator along x, assembles H phi           */
+    BEC_SITE_OTHER,        /* renormalisation of the FP32 phase and anything else                 */
+    BEC_NSITES
+};
+
+/* Measurement helper: runs `iters` iterations of Algorithm 1 from d_phi (overwritten with the
+ * iterate reached) with no stopping test, launching every kernel eagerly with start and stop
+ * events of its own on the stream it runs on, and accumulates per launch site (BEC_SITE_*)
+ * the summed kernel durations in site_ms[BEC_NSITES] (milliseconds) and the launch counts in
+ * site_launches[BEC_NSITES] (host arrays). On BEC_FP32 grids the iterations are those of the
+ * FP32 bulk phase. The initial H phi apply is not counted. Synchronises. */
+int bec_pcg_profile(bec_grid g, const bec_params* p, void* d_phi, int iters, double* site_ms,
+                    int32_t* site_launches);
 
 /* Line tiles of the runtime-length FFT kernels: lengths without register kernels (those have
  * 32..1024 powers of two and 48, 96, 192, 384, 160, 320), or every length when the register

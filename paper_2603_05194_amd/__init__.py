@@ -17,6 +17,10 @@ LIB_PATH = os.path.join(HERE, "libbec.so")
 
 BEC_OK, BEC_EINVAL, BEC_ENOMEM, BEC_EHIP, BEC_ENOTCONV, BEC_ENUMERIC, BEC_ESTALL = 0, -1, -2, -3, -4, -5, -6
 BEC_FP64, BEC_FP32 = 0, 1
+# launch sites of one PCG iteration (bec_pcg_profile), in the order of the BEC_SITE_* enum
+SITES = ("control", "finish", "prec_z", "prec_y", "prec_x", "prec_zi", "dir_z", "y_fwd", "x_pars2", "p_lines",
+         "retract", "atkm_z", "x_atkm", "y_inv", "atkm_zi", "h_z", "h_y", "h_x", "other")
+BEC_NSITES = len(SITES)
 
 
 class bec_grid_desc(C.Structure):
@@ -40,7 +44,7 @@ class bec_pcg_opts(C.Structure):
                 ("max_halvings", C.c_int32), ("t_default", C.c_double), ("tau_E_ulps", C.c_double),
                 ("switch_res", C.c_double), ("check_every", C.c_int32), ("debug_flags", C.c_int32),
                 ("debug_t", C.c_double), ("debug_c2", C.c_double), ("stall_window", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("switch_relative", C.c_int32)]
 
 
 class bec_pcg_result(C.Structure):
@@ -87,6 +91,8 @@ _SIGS = {
     "bec_fft3d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "bec_time_stage": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.c_int,
                                  C.POINTER(C.c_double)]),
+    "bec_pcg_profile": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_int32)]),
     "bec_interp_spectral": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "bec_normalize": (C.c_int, [C.c_void_p, C.c_void_p]),
     "bec_gauge_fix": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p]),
@@ -225,6 +231,13 @@ def bec_time_stage(h, params, d_phi, which, reps) -> float:
     ms = C.c_double(0.0)
     _check(_lib().bec_time_stage(h, _params_arg(params), C.c_void_p(d_phi), which, reps, C.byref(ms)), "bec_time_stage")
     return ms.value
+
+
+def bec_pcg_profile(h, params, d_phi, iters):
+    """{site name: (total ms, launches)} over `iters` eagerly launched, event-timed iterations."""
+    ms, cnt = (C.c_double * BEC_NSITES)(), (C.c_int32 * BEC_NSITES)()
+    _check(_lib().bec_pcg_profile(h, _params_arg(params), C.c_void_p(d_phi), iters, ms, cnt), "bec_pcg_profile")
+    return {SITES[i]: (ms[i], cnt[i]) for i in range(BEC_NSITES)}
 
 
 def bec_set_line_tiles(h, div):
@@ -427,6 +440,14 @@ class BecGrid:
     def time_stage(self, params, phi, which, reps=10):
         self.ensure_symbol()
         return bec_time_stage(self.handle, params, self._field(phi).data_ptr(), which, reps)
+
+    def pcg_profile(self, params, phi, iters):
+        """Per launch site (total ms, launches) over `iters` iterations from phi (updated in place)."""
+        if params.lambda_ != 0.0:
+            self.ensure_symbol()
+        assert self.batch == 1
+        assert phi.is_contiguous() and phi.dtype == self.torch.complex128 and tuple(phi.shape) == self.n
+        return bec_pcg_profile(self.handle, params, phi.data_ptr(), iters)
 
     def set_line_tiles(self, div):
         """Per-axis (x, y, z) divisors of the runtime-length FFT kernels' lines per block."""

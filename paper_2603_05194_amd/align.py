@@ -10,15 +10,24 @@ import math
 
 
 def e2(u, ref):
-    """||u - kappa ref|| / ||ref||, kappa = <u, ref> / <ref, ref> (device tensors)."""
-    import torch
-    kappa = torch.vdot(ref.flatten(), u.flatten()) / torch.vdot(ref.flatten(), ref.flatten())
-    return float(torch.linalg.vector_norm(u - kappa * ref) / torch.linalg.vector_norm(ref))
+    """||u - kappa ref|| / ||ref||, kappa = <u, ref> / <ref, ref>; u and ref are device tensors (or
+    host arrays), the sums are taken on the host in FP64."""
+    import numpy as np
+    a = _host(u).ravel()
+    b = _host(ref).ravel()
+    kappa = np.vdot(b, a) / np.vdot(b, b)
+    return float(np.linalg.norm(a - kappa * b) / np.linalg.norm(b))
+
+
+def _host(t):
+    import numpy as np
+    return t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
 
 
 def e2_tilde(grid, u, ref, period=2.0 * math.pi, scan=72, tol=1e-9):
     """min over alpha of e2(u(R_alpha x), ref) and the minimising alpha; `grid` is the BecGrid of
     u (batch 1, N_x = N_y, a_x = a_y)."""
+    ref = _host(ref)
     f = lambda al: e2(grid.rotate_z(u, al), ref)
     step = period / scan
     vals = [f(i * step) for i in range(scan)]

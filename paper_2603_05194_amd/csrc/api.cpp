@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -432,7 +433,8 @@ int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* 
         // FP32 bulk phase: stop at ||r||_inf <= switch_res or when the residual stalls. The
         // trial energies are FP64 polynomials of FP64 sums, so the energy test keeps its FP64
         // slack (an FP32-sized slack accepts energy increases and the phase never settles).
-        co.tol_res = std::max(o.switch_res, o.tol_res_inf);
+        co.tol_res = o.switch_relative ? o.switch_res : std::max(o.switch_res, o.tol_res_inf);
+        co.tol_rel = o.switch_relative ? 1 : 0;
         co.fp32 = 0;
         launch_ctl_init(g, co);
         e = hipMemsetAsync(g.f32.p, 0, NB * sizeof(cpx<float>), g.stream);
@@ -477,6 +479,41 @@ int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* 
     }
     if (worst != BEC_OK) g_last_error = bec_status_string(worst);
     return worst;
+}
+
+// Iterations of Algorithm 1 with every launch timed by its own events (see bec_pcg_profile).
+// The stream drains after each iteration, when the pairs are read and the pool reused.
+template <typename R>
+int profile_phase(Grid& g, cpx<R>* phi, int iters, double* ms, int32_t* cnt) {
+    launch_pcg_start<R>(g, phi);
+    int rc = check_launch(&g, "profile start");
+    if (rc) return rc;
+    KProf kp;
+    kp.ev.resize(2 * 128);   // at most 128 launches per iteration
+    for (auto& e : kp.ev) {
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) { rc = hip_fail(&g, he, "profile events"); break; }
+    }
+    for (int it = 0; it < iters && !rc; ++it) {
+        kp.sites.clear();
+        g.kprof = &kp;
+        launch_pcg_iteration<R>(g, phi, it & 1);
+        g.kprof = nullptr;
+        if ((rc = check_launch(&g, "profile iteration"))) break;
+        hipError_t he = hipStreamSynchronize(g.stream);
+        if (he != hipSuccess) { rc = hip_fail(&g, he, "profile sync"); break; }
+        for (size_t k = 0; k < kp.sites.size(); ++k) {
+            float t = 0.f;
+            he = hipEventElapsedTime(&t, kp.ev[2 * k], kp.ev[2 * k + 1]);
+            if (he != hipSuccess) { rc = hip_fail(&g, he, "profile elapsed"); break; }
+            ms[kp.sites[k]] += t;
+            cnt[kp.sites[k]] += 1;
+        }
+    }
+    g.kprof = nullptr;
+    for (auto& e : kp.ev)
+        if (e) hipEventDestroy(e);
+    return rc;
 }
 
 }  // namespace
@@ -748,6 +785,7 @@ int bec_pcg_default_opts(bec_pcg_opts* o) {
     o->check_every = 16;
     o->stall_window = 400;
     o->use_graph = 1;
+    o->switch_relative = 1;
     return BEC_OK;
 }
 
@@ -766,6 +804,44 @@ int bec_pcg_solve_batched(bec_grid g, const bec_params* pp, void* d_phi, const b
 
 int bec_pcg_solve(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_opts* opts, bec_pcg_result* res) {
     return bec_pcg_solve_batched(g, pp, d_phi, opts, res);
+}
+
+int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, double* site_ms, int32_t* site_launches) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_phi || !site_ms || !site_launches || iters < 1) return fail(BEC_EINVAL, "bad arguments");
+    if ((rc = upload_params(*g, pp))) return rc;
+    for (int i = 0; i < BEC_NSITES; ++i) { site_ms[i] = 0.0; site_launches[i] = 0; }
+    bec_pcg_opts o;
+    bec_pcg_default_opts(&o);
+    CtlOpts co;
+    co.tol_res = 0.0; co.tol_step = 0.0; co.t_default = o.t_default; co.tau_ulps = o.tau_E_ulps;
+    co.dbg_t = 0.0; co.dbg_c2 = 0.0; co.max_iter = 0x7fffffff; co.max_halv = o.max_halvings;
+    co.dbg_flags = 0; co.fp32 = 0;
+    const size_t NB = (size_t)g->n[0] * g->n[1] * g->n[2] * g->batch;
+    hipError_t e = hipMemsetAsync(g->dstop, 0, g->batch * sizeof(int), g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g->f64.p, 0, NB * sizeof(cpx<double>), g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g->f64.r1, 0, NB * sizeof(cpx<double>), g->stream);
+    if (e == hipSuccess && g->precision == BEC_FP32) e = hipMemsetAsync(g->f32.p, 0, NB * sizeof(cpx<float>), g->stream);
+    if (e == hipSuccess && g->precision == BEC_FP32) e = hipMemsetAsync(g->f32.r1, 0, NB * sizeof(cpx<float>), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "profile init");
+    launch_ctl_init(*g, co);
+    cpx<double>* phi = (cpx<double>*)d_phi;
+    if (g->precision == BEC_FP32) {
+        launch_to_f32(*g, phi, g->f32.phi);
+        rc = profile_phase<float>(*g, g->f32.phi, iters, site_ms, site_launches);
+        if (!rc) {
+            launch_ctl_phase(*g, o.tol_res_inf, o.max_iter, o.tau_E_ulps, 2.220446049250313e-16);
+            launch_to_f64_normalized(*g, g->f32.phi, phi);
+            rc = check_launch(g, "profile convert");
+        }
+    } else {
+        rc = profile_phase<double>(*g, phi, iters, site_ms, site_launches);
+    }
+    if (rc) return rc;
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "profile sync");
+    return BEC_OK;
 }
 
 int bec_time_stage(bec_grid g, const bec_params* pp, const void* d_phi, int which, int reps, double* avg_ms) {
@@ -853,3 +929,4 @@ int bec_autotune_line_tiles(bec_grid g, const bec_params* pp, const void* d_phi,
 }
 
 }  // extern "C"
+

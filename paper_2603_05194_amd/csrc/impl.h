@@ -2,6 +2,7 @@
 #pragma once
 #include <string>
 #include <vector>
+#include "../../include/bec.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -63,6 +64,25 @@ struct Grid {
     // recording its own start and end (stage timing)
     hipEvent_t tev0 = nullptr, tev1 = nullptr;
     Bat bt64, bt32;           // per-solve strides of the FP64 / FP32 buffers
+    // in-iteration profile: when kprof is set, every launch takes a pair of events from its pool
+    // and is recorded under the launch site in `site` (see bec_pcg_profile)
+    int site = 0;
+    struct KProf* kprof = nullptr;
+};
+
+// Event pool of an in-iteration profile: pairs are handed out in launch order and harvested
+// (elapsed time per site) after the stream has drained.
+struct KProf {
+    std::vector<hipEvent_t> ev;   // 2 * capacity events
+    std::vector<int> sites;       // site of each pair handed out
+    bool take(int site, hipEvent_t& a, hipEvent_t& b) {
+        const size_t k = sites.size();
+        if (2 * k + 1 >= ev.size()) return false;   // pool exhausted: the launch goes untimed
+        a = ev[2 * k];
+        b = ev[2 * k + 1];
+        sites.push_back(site);
+        return true;
+    }
 };
 
 template <typename R> inline Fields<R>& fields(Grid& g);
@@ -81,6 +101,7 @@ void launch_set_params(Grid& g);   // copies g.dparams[b] into st[b] (already up
 struct CtlOpts {
     double tol_res, tol_step, t_default, tau_ulps, dbg_t, dbg_c2;
     int max_iter, max_halv, dbg_flags, fp32;
+    int tol_rel = 0;   // stop at ||r||_inf <= tol_res |mu| (the FP32 phase's switch)
 };
 template <typename R> void launch_pcg_iteration(Grid& g, cpx<R>* phi, int parity);
 template <typename R> void launch_pcg_start(Grid& g, cpx<R>* phi);

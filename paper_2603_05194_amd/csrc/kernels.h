@@ -38,6 +38,7 @@ struct DevState {
     double tau_E, eps_E;
     // options
     double tol_res, tol_step, t_default, tau_ulps;
+    int tol_rel;                   // 1: tol_res is relative to |mu|
     double dbg_t, dbg_c2;
     int max_iter, max_halv, dbg_flags;
     // counters and flags

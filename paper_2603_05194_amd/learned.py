@@ -99,12 +99,11 @@ def solve_batch(draws, n, guesses, precision, opts):
 
 
 def boundary_ratio(phis):
-    """max |phi| on the six boundary planes over max |phi|, per field (data check only)."""
-    m = phis.abs()
+    """max |phi| on the six boundary planes over max |phi|, per field (data check only, on the host)."""
+    m = np.abs(phis.cpu().numpy() if hasattr(phis, "cpu") else np.asarray(phis))
     planes = [m[:, 0], m[:, -1], m[:, :, 0], m[:, :, -1], m[:, :, :, 0], m[:, :, :, -1]]
-    import torch
-    edge = torch.stack([p.flatten(1).amax(1) for p in planes]).amax(0)
-    return (edge / m.flatten(1).amax(1)).cpu().numpy()
+    edge = np.stack([p.reshape(p.shape[0], -1).max(1) for p in planes]).max(0)
+    return edge / m.reshape(m.shape[0], -1).max(1)
 
 
 def generate(draws, max_iter=4000, batch=64, tol=1e-8, log=None):
@@ -211,8 +210,13 @@ def evaluate(net, draws, n, precision=BEC_FP32, max_iter=200000, log=None):
         gs = [plain_guess(d, n) for d in ds]
         g0, _, r0, t0 = solve_batch(ds, n, gs, precision, opts)
         del g0
-        lg = predict(net, ds, n).cpu().numpy()
-        g1, _, r1, t1 = solve_batch(ds, n, list(lg), precision, opts)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        lg = predict(net, ds, n)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - tp
+        g1, _, r1, t1 = solve_batch(ds, n, list(lg.cpu().numpy()), precision, opts)
+        t1 += t_pred            # the network and the interpolation belong to the learned start's time
         del g1
         for k, i in enumerate(idx):
             rows[i] = dict(band=band, draw=[float(v) for v in draws[i]],

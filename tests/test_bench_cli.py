@@ -25,3 +25,19 @@ def test_pass_bytes_match_the_layout_model():
     assert bench.pass_bytes("y_fwd", n, 16) == zh + yb == 204472320
     assert bench.pass_bytes("x_pass", n, 16) == 2 * yb + octant
     assert bench.pass_bytes("x_pars2", n, 16) == 2 * yb + octant
+
+
+def test_site_bytes_cover_the_iteration():
+    """Per-site algorithmic bytes of one FP64 iteration at 256x256x64 add up to the pass model
+    (about 4.3 GB: every field read and written once per pass)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import paper_2603_05194_amd as bec
+    n = (256, 256, 64)
+    per_launch = {s: bench.site_bytes(s, n, 16) for s in bec.SITES}
+    launches = {"prec_y": 2, "y_fwd": 3, "p_lines": 3}
+    total = sum(b * launches.get(s, 1) for s, b in per_launch.items())
+    assert per_launch["control"] == per_launch["finish"] == 0
+    assert per_launch["y_fwd"] == bench.pass_bytes("y_fwd", n, 16)
+    assert per_launch["x_atkm"] == per_launch["x_pars2"] == bench.pass_bytes("x_pass", n, 16)
+    assert 4.2e9 < total < 4.4e9
