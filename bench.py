@@ -88,13 +88,15 @@ def site_bytes(site, n, csize, lam=True):
     }.get(site, 0)
 
 
-# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (FETCH_SIZE scaled by the copy-kernel
-# calibration factor 2.0, WRITE_SIZE by 1.0), taken with the kernel sources hashing to `src`; null
-# once the sources have changed.
+# HBM bytes per launch and site from rocprofv3 FETCH_SIZE / WRITE_SIZE (FETCH_SIZE scaled by the
+# copy-kernel calibration factor 2.0, WRITE_SIZE by 1.0), taken with the kernel sources hashing to
+# MEASURED_TRAFFIC_SRC; the roofline's traffic is null once the sources have changed.
+MEASURED_TRAFFIC_SRC = "78cbcd91169de4df"
 MEASURED_TRAFFIC = {
-    "y_fwd": {"bytes": 214.1e6, "src": "3f3d46f6af5c5135"},
-    "x_atkm": {"bytes": 355.4e6, "src": "3f3d46f6af5c5135"},
-    "x_pars2": {"bytes": 367.6e6, "src": "3f3d46f6af5c5135"},
+    "atkm_z": 136.4e6, "y_fwd": 214.1e6, "x_atkm": 355.4e6, "y_inv": 220.4e6,
+    "atkm_zi": 127.5e6, "h_z": 134.4e6, "h_y": 201.5e6, "h_x": 327.2e6,
+    "prec_z": 302.2e6, "prec_y": 134.3e6, "prec_x": 134.4e6, "prec_zi": 513.1e6,
+    "dir_z": 440.9e6, "x_pars2": 367.6e6, "p_lines": 67.3e6, "retract": 201.4e6,
 }
 
 
@@ -325,7 +327,7 @@ def main():
         del gm
 
     ds = sites[dom]
-    src_ok = MEASURED_TRAFFIC.get(dom, {}).get("src") == kernel_src_hash()
+    src_ok = dom in MEASURED_TRAFFIC and MEASURED_TRAFFIC_SRC == kernel_src_hash()
     out = {
         "metric": METRIC,
         "value": t_solve,
@@ -354,7 +356,7 @@ def main():
         "symbol_precompute_s": t_symbol,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ds["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ds["achieved_GBs"] / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC[dom]["bytes"] if src_ok else None,
+                     "traffic": MEASURED_TRAFFIC[dom] if src_ok else None,
                      "algorithmic_bytes": ds["bytes_per_launch"], "avg_us": ds["avg_us"],
                      "launches_per_iter": ds["launches_per_iter"]},
         "sites": sites,
