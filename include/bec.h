@@ -131,6 +131,21 @@ int bec_dipolar(bec_grid g, const bec_params* p, const void* d_phi, void* d_Phi)
 int bec_apply_H(bec_grid g, const bec_params* p, const void* d_phi, void* d_hphi,
                 void* d_Phi, double* d_mu);
 
+/* bec_apply_H for callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): no handle and no workspace argument. The
+ * workspace is a static device array of bec_static_scratch_bytes() bytes (64 MiB), one per GPU,
+ * held until the process ends; the grid's workspace (bec_workspace_bytes for BEC_FP64) must fit
+ * in it, else BEC_EINVAL. FP64 fields only (complex128 d_phi, d_hphi; double d_Phi). The truncated-
+ * kernel symbol is computed on the first call for a grid and kept until a call with another grid
+ * or box. Work is enqueued on `hip_stream` (a hipStream_t or NULL), on the current device. All
+ * calls on one GPU share its array: calls that overlap in time on one GPU (other streams or
+ * threads without ordering) race and must be serialised by the caller. The first call on a device,
+ * and a call whose grid differs from the previous call's, also upload twiddle tables and may
+ * compute the symbol (synchronous copies); repeated calls on one grid only launch kernels. */
+int bec_apply_H_static(const bec_grid_desc* desc, const bec_params* p, const void* d_phi, void* d_hphi,
+                       void* d_Phi, double* d_mu, void* hip_stream);
+int bec_static_scratch_bytes(size_t* bytes);
+
 /* Energy parts of phi (Sec. 2.3 discrete energy; Sec. 3 virial identity). `out` is a host
  * pointer if out_on_host != 0 (the call then synchronises), else a device pointer. */
 int bec_energy(bec_grid g, const bec_params* p, const void* d_phi, bec_energies* out,

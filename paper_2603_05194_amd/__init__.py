@@ -85,6 +85,9 @@ _SIGS = {
     "bec_dipolar": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_void_p]),
     "bec_apply_H": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bec_energy": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_void_p, C.c_int]),
+    "bec_apply_H_static": (C.c_int, [C.POINTER(bec_grid_desc), C.POINTER(bec_params), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bec_static_scratch_bytes": (C.c_int, [C.POINTER(C.c_size_t)]),
     "bec_pcg_solve": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.POINTER(bec_pcg_opts),
                                 C.POINTER(bec_pcg_result)]),
     "bec_pcg_default_opts": (C.c_int, [C.POINTER(bec_pcg_opts)]),
@@ -186,6 +189,18 @@ def bec_apply_H(h, params, d_phi, d_hphi, d_Phi=None, d_mu=None):
     _check(_lib().bec_apply_H(h, _params_arg(params), C.c_void_p(d_phi), C.c_void_p(d_hphi),
                               C.c_void_p(d_Phi) if d_Phi else None, C.c_void_p(d_mu) if d_mu else None),
            "bec_apply_H")
+
+
+def bec_apply_H_static(desc, params, d_phi, d_hphi, d_Phi=None, d_mu=None, stream=None):
+    _check(_lib().bec_apply_H_static(C.byref(desc), C.byref(params), C.c_void_p(d_phi), C.c_void_p(d_hphi),
+                                     C.c_void_p(d_Phi) if d_Phi else None, C.c_void_p(d_mu) if d_mu else None,
+                                     C.c_void_p(stream) if stream else None), "bec_apply_H_static")
+
+
+def bec_static_scratch_bytes() -> int:
+    out = C.c_size_t(0)
+    _check(_lib().bec_static_scratch_bytes(C.byref(out)), "bec_static_scratch_bytes")
+    return out.value
 
 
 def _params_arg(params):

@@ -930,3 +930,4 @@ int bec_autotune_line_tiles(bec_grid g, const bec_params* pp, const void* d_phi,
 
 }  // extern "C"
 
+#include "static_apply.inc"
