@@ -327,6 +327,25 @@ int read_states(Grid& g, std::vector<DevState>& hs) {
     return BEC_OK;
 }
 
+// The solver's auxiliary stream and fork/join events (parallel branches of the iteration).
+int open_branches(Grid& g) {
+    hipError_t e = hipStreamCreateWithFlags(&g.aux, hipStreamNonBlocking);
+    for (int k = 0; k < kBranchEvents && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&g.ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(&g, e, "branch stream");
+    return BEC_OK;
+}
+
+void close_branches(Grid& g) {
+    if (g.aux) {
+        (void)hipStreamSynchronize(g.aux);
+        (void)hipStreamDestroy(g.aux);
+    }
+    for (int k = 0; k < kBranchEvents; ++k)
+        if (g.ev[k]) (void)hipEventDestroy(g.ev[k]);
+    g.aux = nullptr;
+    for (int k = 0; k < kBranchEvents; ++k) g.ev[k] = nullptr;
+}
+
 // ------------------------------------------------------------------ PCG driver
 // Runs Algorithm 1 for every solve of the batch with all scalar decisions on the device. The
 // host enqueues iterations (eagerly for the first two, then as a captured two-iteration HIP
@@ -417,6 +436,14 @@ int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* 
     if (e == hipSuccess) e = hipStreamWaitEvent(ps, ev, 0);
     if (e != hipSuccess) return hip_fail(&g, e, "solve stream");
     g.stream = ps;
+    int brc = open_branches(g);
+    if (brc) {
+        close_branches(g);
+        g.stream = user;
+        (void)hipEventDestroy(ev);
+        (void)hipStreamDestroy(ps);
+        return brc;
+    }
     const size_t NB = (size_t)g.n[0] * g.n[1] * g.n[2] * g.batch;
     CtlOpts co;
     co.tol_res = o.tol_res_inf; co.tol_step = o.tol_step_inf; co.t_default = o.t_default; co.tau_ulps = o.tau_E_ulps;
@@ -455,10 +482,11 @@ int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* 
         launch_ctl_init(g, co);
         rc = pcg_phase<double>(g, phi, o, false, hs);
     }
-    hipStreamSynchronize(ps);
+    (void)hipStreamSynchronize(ps);
+    close_branches(g);
     g.stream = user;
-    hipEventDestroy(ev);
-    hipStreamDestroy(ps);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(ps);
     if (rc) return rc;
     int worst = BEC_OK;
     for (int b = 0; b < g.batch; ++b) {
@@ -826,6 +854,10 @@ int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, do
     if (e == hipSuccess && g->precision == BEC_FP32) e = hipMemsetAsync(g->f32.r1, 0, NB * sizeof(cpx<float>), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "profile init");
     launch_ctl_init(*g, co);
+    if ((rc = open_branches(*g))) {
+        close_branches(*g);
+        return rc;
+    }
     cpx<double>* phi = (cpx<double>*)d_phi;
     if (g->precision == BEC_FP32) {
         launch_to_f32(*g, phi, g->f32.phi);
@@ -838,6 +870,7 @@ int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, do
     } else {
         rc = profile_phase<double>(*g, phi, iters, site_ms, site_launches);
     }
+    close_branches(*g);
     if (rc) return rc;
     e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "profile sync");

@@ -33,6 +33,8 @@ template <typename R> struct Fields {
     FftPlan pz, py, px, pzp, pyp, pxp;   // twiddle tables in this precision
 };
 
+constexpr int kBranchEvents = 8;   // fork/join events per iteration (distinct points)
+
 struct Grid {
     int n[3];
     double a[3], h[3], h3;
@@ -68,6 +70,10 @@ struct Grid {
     // and is recorded under the launch site in `site` (see bec_pcg_profile)
     int site = 0;
     struct KProf* kprof = nullptr;
+    // second stream and fork/join events of the solver (null outside bec_pcg_solve / profile):
+    // passes that do not depend on each other run as parallel branches of the iteration
+    hipStream_t aux = nullptr;
+    hipEvent_t ev[kBranchEvents] = {};
 };
 
 // Event pool of an in-iteration profile: pairs are handed out in launch order and harvested
