@@ -1,0 +1,29 @@
+"""What the trained network gains over the plain start: Algorithm 1 from the plain guess
+(phi_d of the trap Gaussian) and from the network's guess (network -> coarse field -> spectral
+interpolation -> unit mass, counted in the learned start's time) on held-out draws at
+128 x 128 x 32, FP32 bulk + FP64 polish, batched per gamma_z band. The final energy judges the
+network: a draw that ends higher than from the plain guess is a loss."""
+import pytest
+
+import bec_inputs as bi
+from tests.gpu_util import torch_mod
+
+pytestmark = pytest.mark.gpu
+
+DRAWS = 24          # held-out seeds 10^6 + 0 .. 10^6 + 23
+GRID = (128, 128, 32)
+
+
+def test_learned_start_gains_on_held_out_draws():
+    torch_mod()
+    from paper_2603_05194_amd import learned as L
+    net = L.load_default()
+    val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(DRAWS)]
+    print(f"learned vs plain on {DRAWS} held-out draws at {GRID}", flush=True)
+    rows = L.evaluate(net, val, GRID, max_iter=30000, log=lambda s: print(s, flush=True))
+    s = L.summarize(rows)
+    print(f"summary: {s}")
+    assert s["both_converged"] >= DRAWS - 2
+    # the gain measured on these draws: fewer iterations on most draws and in the median
+    assert s["iter_ratio_median"] < 0.95
+    assert s["learned_fewer_iters"] > s["both_converged"] // 2
