@@ -14,9 +14,13 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--block B] [--budget S] [--
   Its iteration cap comes from the wall budget (--budget seconds from the start of the script,
   default 540) and the measured iteration rate, so the JSON line is always printed; a capped
   solve is reported as such (`solve.status`).
-* The roofline kernel is the launch site with the largest kernel time per iteration in an
-  event-timed profile of 50 iterations (bec_pcg_profile: every launch has start and stop events
-  of its own on the stream it runs on); achieved = algorithmic bytes per launch / mean duration.
+* The solver runs passes that do not depend on each other on a second stream (graph branches);
+  the timed blocks and `value` use it. Kernel durations taken beside other kernels include the
+  sharing of the GPU, so the roofline kernel is taken from an event-timed profile of 50
+  iterations launched in order on one stream (bec_pcg_profile, every launch with start and stop
+  events of its own): the launch site with the largest kernel time per iteration; achieved =
+  algorithmic bytes per launch / mean duration. Three more blocks on one stream give the rate
+  without the branches (pcg_iters_per_s_one_stream).
 * The learned leg (network + spectral interpolation + FP32 bulk + FP64 polish, all inside the
   timed region) runs only if the budget allows; its speed-up against the FP64 solve is reported
   only when both end in the same state (|dE| <= 1e-10 |E|).
@@ -224,7 +228,7 @@ def main():
     log(f"{args.steps} blocks of {args.block}: {t_blocks:.3f}s, {it_per_s:.1f} it/s, res {blocks[-1].res_inf:.2e}")
 
     # ---------------------------------------------------------------- per-kernel profile in the iteration
-    prof = g.pcg_profile(p, phi_b, args.profile_iters)
+    prof = g.pcg_profile(p, phi_b, args.profile_iters, concurrent=False)
     sites = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
@@ -239,7 +243,17 @@ def main():
     for k, s in sorted(sites.items(), key=lambda kv: -kv[1]["us_per_iter"]):
         log(f"  {k:9s} {s['us_per_iter']:8.1f} us/it  {s['avg_us']:7.1f} us/launch  "
             + (f"{s['achieved_GBs']:6.0f} GB/s" if s["achieved_GBs"] else ""))
-    log(f"kernel time per iteration {kern_us:.1f} us; dominant {dom}")
+    log(f"kernel time per iteration {kern_us:.1f} us (one stream); dominant {dom}")
+    o1 = bec.bec_pcg_default_opts()
+    o1.tol_res_inf = 0.0
+    o1.max_iter = args.block
+    o1.branches = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it1 = sum(g.pcg_solve(p, phi_b, o1).iters for _ in range(3))
+    torch.cuda.synchronize()
+    it_per_s_1 = it1 / (time.perf_counter() - t0)
+    log(f"one stream: {it_per_s_1:.1f} it/s")
 
     t_apply_ms = g.time_stage(p, phi_b, 2, reps=20)
     t_atkm_ms = g.time_stage(p, phi_b, 1, reps=20)
@@ -350,6 +364,7 @@ def main():
                   "E": ref.e.E, "mu": ref.e.mu, "iter_cap": opts.max_iter,
                   "note": None if converged else "iteration cap from the wall budget reached: not a ground state"},
         "pcg_iters_per_s": it_per_s,
+        "pcg_iters_per_s_one_stream": it_per_s_1,
         "hphi_per_s": 1e3 / t_apply_ms,
         "atkm_per_s": 1e3 / t_atkm_ms,
         "kernel_us_per_iter": kern_us,

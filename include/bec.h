@@ -84,6 +84,8 @@ typedef struct {
     int32_t stall_window;  /* mixed: switch to FP64 if ||r||_inf has not improved this long   */
     int32_t use_graph;     /* 1: replay iterations from a captured HIP graph (default 1)     */
     int32_t switch_relative; /* 1 (default): the FP32 -> FP64 switch is ||r||_inf <= switch_res |mu| */
+    int32_t branches;      /* 1 (default): passes that do not depend on each other run on a second */
+                           /* stream beside the others; 0: every launch in order on one stream    */
 } bec_pcg_opts;
 
 typedef struct {
@@ -239,10 +241,33 @@ enum {
  * iterate reached) with no stopping test, launching every kernel eagerly with start and stop
  * events of its own on the stream it runs on, and accumulates per launch site (BEC_SITE_*)
  * the summed kernel durations in site_ms[BEC_NSITES] (milliseconds) and the launch counts in
- * site_launches[BEC_NSITES] (host arrays). On BEC_FP32 grids the iterations are those of the
- * FP32 bulk phase. The initial H phi apply is not counted. Synchronises. */
-int bec_pcg_profile(bec_grid g, const bec_params* p, void* d_phi, int iters, double* site_ms,
+ * site_launches[BEC_NSITES] (host arrays). flags bit 0: run the independent passes on a second
+ * stream as the solver does (durations then include the sharing of the GPU); clear: every
+ * launch in order on one stream (each kernel's own duration). On BEC_FP32 grids the iterations
+ * are those of the FP32 bulk phase. The initial H phi apply is not counted. Synchronises. */
+int bec_pcg_profile(bec_grid g, const bec_params* p, void* d_phi, int iters, int flags, double* site_ms,
                     int32_t* site_launches);
+
+/* Launch-shape variants of the register-resident FFT kernels, per launch site (BEC_SITE_*):
+ * 0 is the default shape; bit 0 halves the points per thread in blocks of twice the threads;
+ * bit 1 exchanges whole complex values through LDS where the default exchanges one component at
+ * a time (larger LDS tile, fewer barriers). For the two-density Parseval pass bit 0 selects the
+ * line kernels' shape instead of its own. Lines per block, tiles, radices and every butterfly
+ * stay the same, so fields are identical bit for bit under every variant; block sums group the
+ * points by thread, so reductions change at rounding level. Variants exist for the power-of-two
+ * lengths of at least 16 points per thread and for lengths whose default tile uses the split
+ * exchange; other sites ignore the setting. A project addition (performance only, no passage of
+ * the paper). Arrays hold BEC_NSITES entries. */
+int bec_set_kernel_variants(bec_grid g, const int32_t* variants);
+int bec_get_kernel_variants(bec_grid g, int32_t* variants);
+/* Times every variant on every launch site with `iters` event-timed iterations of Algorithm 1
+ * each (as bec_pcg_profile on one stream, from d_phi, which is overwritten), keeps per site that
+ * has variants the fastest one if it beats the default by more than 2 %, leaves the choice on
+ * the grid and
+ * returns it in variants_out; ms_default / ms_best receive the per-iteration milliseconds of
+ * each site under the default and the chosen variant (all three nullable). Synchronises. */
+int bec_autotune_kernels(bec_grid g, const bec_params* p, void* d_phi, int iters, int32_t* variants_out,
+                         double* ms_default, double* ms_best);
 
 /* Line tiles of the runtime-length FFT kernels: lengths without register kernels (those have
  * 32..1024 powers of two and 48, 96, 192, 384, 160, 320), or every length when the register

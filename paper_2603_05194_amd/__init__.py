@@ -44,7 +44,7 @@ class bec_pcg_opts(C.Structure):
                 ("max_halvings", C.c_int32), ("t_default", C.c_double), ("tau_E_ulps", C.c_double),
                 ("switch_res", C.c_double), ("check_every", C.c_int32), ("debug_flags", C.c_int32),
                 ("debug_t", C.c_double), ("debug_c2", C.c_double), ("stall_window", C.c_int32),
-                ("use_graph", C.c_int32), ("switch_relative", C.c_int32)]
+                ("use_graph", C.c_int32), ("switch_relative", C.c_int32), ("branches", C.c_int32)]
 
 
 class bec_pcg_result(C.Structure):
@@ -94,12 +94,16 @@ _SIGS = {
     "bec_fft3d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "bec_time_stage": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.c_int,
                                  C.POINTER(C.c_double)]),
-    "bec_pcg_profile": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.POINTER(C.c_double),
-                                  C.POINTER(C.c_int32)]),
+    "bec_pcg_profile": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "bec_interp_spectral": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "bec_normalize": (C.c_int, [C.c_void_p, C.c_void_p]),
     "bec_gauge_fix": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p]),
     "bec_rotate_z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    "bec_set_kernel_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "bec_get_kernel_variants": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "bec_autotune_kernels": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "bec_set_line_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "bec_get_line_tiles": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "bec_autotune_line_tiles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int32),
@@ -248,11 +252,32 @@ def bec_time_stage(h, params, d_phi, which, reps) -> float:
     return ms.value
 
 
-def bec_pcg_profile(h, params, d_phi, iters):
-    """{site name: (total ms, launches)} over `iters` eagerly launched, event-timed iterations."""
+def bec_pcg_profile(h, params, d_phi, iters, flags=0):
+    """{site name: (total ms, launches)} over `iters` eagerly launched, event-timed iterations
+    (flags bit 0: with the solver's second stream)."""
     ms, cnt = (C.c_double * BEC_NSITES)(), (C.c_int32 * BEC_NSITES)()
-    _check(_lib().bec_pcg_profile(h, _params_arg(params), C.c_void_p(d_phi), iters, ms, cnt), "bec_pcg_profile")
+    _check(_lib().bec_pcg_profile(h, _params_arg(params), C.c_void_p(d_phi), iters, flags, ms, cnt),
+           "bec_pcg_profile")
     return {SITES[i]: (ms[i], cnt[i]) for i in range(BEC_NSITES)}
+
+
+def bec_set_kernel_variants(h, variants):
+    arr = (C.c_int32 * BEC_NSITES)(*[int(v) for v in variants])
+    _check(_lib().bec_set_kernel_variants(h, arr), "bec_set_kernel_variants")
+
+
+def bec_get_kernel_variants(h):
+    arr = (C.c_int32 * BEC_NSITES)()
+    _check(_lib().bec_get_kernel_variants(h, arr), "bec_get_kernel_variants")
+    return tuple(arr)
+
+
+def bec_autotune_kernels(h, params, d_phi, iters):
+    """(variants, ms_default, ms_best), each a tuple over the launch sites."""
+    v, d, b = (C.c_int32 * BEC_NSITES)(), (C.c_double * BEC_NSITES)(), (C.c_double * BEC_NSITES)()
+    _check(_lib().bec_autotune_kernels(h, _params_arg(params), C.c_void_p(d_phi), iters, v, d, b),
+           "bec_autotune_kernels")
+    return tuple(v), tuple(d), tuple(b)
 
 
 def bec_set_line_tiles(h, div):
@@ -456,13 +481,14 @@ class BecGrid:
         self.ensure_symbol()
         return bec_time_stage(self.handle, params, self._field(phi).data_ptr(), which, reps)
 
-    def pcg_profile(self, params, phi, iters):
-        """Per launch site (total ms, launches) over `iters` iterations from phi (updated in place)."""
+    def pcg_profile(self, params, phi, iters, concurrent=False):
+        """Per launch site (total ms, launches) over `iters` iterations from phi (updated in place);
+        concurrent: with the solver's second stream."""
         if params.lambda_ != 0.0:
             self.ensure_symbol()
         assert self.batch == 1
         assert phi.is_contiguous() and phi.dtype == self.torch.complex128 and tuple(phi.shape) == self.n
-        return bec_pcg_profile(self.handle, params, phi.data_ptr(), iters)
+        return bec_pcg_profile(self.handle, params, phi.data_ptr(), iters, 1 if concurrent else 0)
 
     def set_line_tiles(self, div):
         """Per-axis (x, y, z) divisors of the runtime-length FFT kernels' lines per block."""
@@ -471,6 +497,49 @@ class BecGrid:
     def line_tiles(self):
         """((div_x, div_y, div_z), (tunable_x, tunable_y, tunable_z))."""
         return bec_get_line_tiles(self.handle)
+
+    def kernel_variants(self):
+        return dict(zip(SITES, bec_get_kernel_variants(self.handle)))
+
+    def set_kernel_variants(self, variants):
+        """variants: a {site: variant} dict (missing sites 0) or a sequence over SITES."""
+        if isinstance(variants, dict):
+            variants = [int(variants.get(s, 0)) for s in SITES]
+        bec_set_kernel_variants(self.handle, variants)
+
+    def autotune_kernels(self, params, phi_scratch, iters=10, cache=None, log=None):
+        """Pick the launch-shape variant of each launch site (bec_autotune_kernels) by timing
+        `iters` iterations per variant from phi_scratch (overwritten). With `cache` (a JSON file) a
+        stored choice for this device, precision and grid is applied without timing, and a new
+        search is stored. Returns ({site: variant}, {site: (ms default, ms chosen)} or None)."""
+        import json
+        import os
+        key = "kernels|" + self.tile_key()
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                store = json.load(fh)
+            if key in store:
+                self.set_kernel_variants(store[key]["variants"])
+                return dict(store[key]["variants"]), None
+        self.ensure_symbol()
+        if self.batch > 1 or not isinstance(params, bec_params):
+            params = (bec_params * self.batch)(*params)
+        v, d, b = bec_autotune_kernels(self.handle, params, phi_scratch.data_ptr(), iters)
+        chosen = {s: v[i] for i, s in enumerate(SITES) if v[i]}
+        times = {s: (d[i], b[i]) for i, s in enumerate(SITES) if d[i] > 0}
+        if log:
+            for s, (a, c) in times.items():
+                if s in chosen:
+                    log(f"kernel variant {key} {s}: {chosen[s]} ({a * 1e3:.1f} -> {c * 1e3:.1f} us per iteration)")
+        if cache:
+            store[key] = dict(variants=chosen, ms={s: list(t) for s, t in times.items()})
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(store, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return chosen, times
 
     def tile_key(self):
         torch = self.torch

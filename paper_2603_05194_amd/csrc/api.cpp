@@ -436,7 +436,8 @@ int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* 
     if (e == hipSuccess) e = hipStreamWaitEvent(ps, ev, 0);
     if (e != hipSuccess) return hip_fail(&g, e, "solve stream");
     g.stream = ps;
-    int brc = open_branches(g);
+    g.step_rule = o.tol_step_inf > 0.0;
+    int brc = o.branches ? open_branches(g) : BEC_OK;
     if (brc) {
         close_branches(g);
         g.stream = user;
@@ -499,7 +500,7 @@ int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* 
         r.forced_accepts = S.forced;
         r.fp32_iters = g.precision == BEC_FP32 ? S.fp32_iters : 0;
         r.res_inf = S.res_inf;
-        r.step_inf = S.step_inf;
+        r.step_inf = g.step_rule || g.precision == BEC_FP32 ? S.step_inf : 0.0;
         r.e.E = S.E; r.e.Ekin = S.Ekin; r.e.Epot = S.Epot; r.e.Eint = S.Eint;
         r.e.Edip = S.Edip; r.e.Erot = S.Erot; r.e.mu = S.mu; r.e.mass = S.mass;
         r.e.virial = 2 * S.Ekin - 2 * S.Epot + 3 * S.Eint + 3 * S.Edip;
@@ -814,6 +815,7 @@ int bec_pcg_default_opts(bec_pcg_opts* o) {
     o->stall_window = 400;
     o->use_graph = 1;
     o->switch_relative = 1;
+    o->branches = 1;
     return BEC_OK;
 }
 
@@ -834,11 +836,13 @@ int bec_pcg_solve(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_o
     return bec_pcg_solve_batched(g, pp, d_phi, opts, res);
 }
 
-int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, double* site_ms, int32_t* site_launches) {
-    int rc = check_grid(g);
-    if (rc) return rc;
-    if (!d_phi || !site_ms || !site_launches || iters < 1) return fail(BEC_EINVAL, "bad arguments");
-    if ((rc = upload_params(*g, pp))) return rc;
+}  // extern "C"
+
+namespace {
+
+// The iterations of bec_pcg_profile on a grid whose parameters are uploaded.
+int run_profile(bec_grid g, void* d_phi, int iters, int flags, double* site_ms, int32_t* site_launches) {
+    int rc = BEC_OK;
     for (int i = 0; i < BEC_NSITES; ++i) { site_ms[i] = 0.0; site_launches[i] = 0; }
     bec_pcg_opts o;
     bec_pcg_default_opts(&o);
@@ -846,6 +850,7 @@ int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, do
     co.tol_res = 0.0; co.tol_step = 0.0; co.t_default = o.t_default; co.tau_ulps = o.tau_E_ulps;
     co.dbg_t = 0.0; co.dbg_c2 = 0.0; co.max_iter = 0x7fffffff; co.max_halv = o.max_halvings;
     co.dbg_flags = 0; co.fp32 = 0;
+    g->step_rule = false;
     const size_t NB = (size_t)g->n[0] * g->n[1] * g->n[2] * g->batch;
     hipError_t e = hipMemsetAsync(g->dstop, 0, g->batch * sizeof(int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->f64.p, 0, NB * sizeof(cpx<double>), g->stream);
@@ -854,7 +859,7 @@ int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, do
     if (e == hipSuccess && g->precision == BEC_FP32) e = hipMemsetAsync(g->f32.r1, 0, NB * sizeof(cpx<float>), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "profile init");
     launch_ctl_init(*g, co);
-    if ((rc = open_branches(*g))) {
+    if ((flags & 1) && (rc = open_branches(*g))) {
         close_branches(*g);
         return rc;
     }
@@ -871,10 +876,71 @@ int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, do
         rc = profile_phase<double>(*g, phi, iters, site_ms, site_launches);
     }
     close_branches(*g);
+    g->step_rule = false;
     if (rc) return rc;
     e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "profile sync");
     return BEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, int flags, double* site_ms,
+                    int32_t* site_launches) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_phi || !site_ms || !site_launches || iters < 1) return fail(BEC_EINVAL, "bad arguments");
+    if ((rc = upload_params(*g, pp))) return rc;
+    return run_profile(g, d_phi, iters, flags, site_ms, site_launches);
+}
+
+int bec_set_kernel_variants(bec_grid g, const int32_t* variants) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!variants) return fail(BEC_EINVAL, "variants is NULL");
+    for (int s = 0; s < BEC_NSITES; ++s)
+        if (variants[s] < 0 || variants[s] >= kKernelVariants) return fail(BEC_EINVAL, "kernel variant out of range");
+    for (int s = 0; s < BEC_NSITES; ++s) g->variant[s] = variants[s];
+    return BEC_OK;
+}
+
+int bec_get_kernel_variants(bec_grid g, int32_t* variants) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!variants) return fail(BEC_EINVAL, "variants is NULL");
+    for (int s = 0; s < BEC_NSITES; ++s) variants[s] = g->variant[s];
+    return BEC_OK;
+}
+
+// Every variant is profiled on every site at once (the sites are different kernels), `iters`
+// iterations each, one stream; each site keeps its fastest variant.
+int bec_autotune_kernels(bec_grid g, const bec_params* pp, void* d_phi, int iters, int32_t* variants_out,
+                         double* ms_default, double* ms_best) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!d_phi || iters < 1) return fail(BEC_EINVAL, "bad arguments");
+    if (!g->have_symbol) return fail(BEC_EINVAL, "bec_atkm_symbol has not been called on this grid");
+    if ((rc = upload_params(*g, pp))) return rc;
+    double ms[kKernelVariants][BEC_NSITES];
+    int32_t cnt[BEC_NSITES];
+    for (int v = 0; v < kKernelVariants && !rc; ++v) {
+        for (int s = 0; s < BEC_NSITES; ++s) g->variant[s] = v;
+        rc = run_profile(g, d_phi, iters, 0, ms[v], cnt);
+    }
+    for (int s = 0; s < BEC_NSITES; ++s) {
+        // a variant replaces the default only when it is faster by more than the run-to-run spread
+        int best = 0;
+        if (!rc && site_has_variants(*g, s))
+            for (int v = 1; v < kKernelVariants; ++v)
+                if (ms[v][s] < 0.98 * ms[0][s] && ms[v][s] < ms[best][s]) best = v;
+        g->variant[s] = best;
+        if (variants_out) variants_out[s] = best;
+        if (ms_default) ms_default[s] = rc ? 0.0 : ms[0][s] / iters;
+        if (ms_best) ms_best[s] = rc ? 0.0 : ms[best][s] / iters;
+    }
+    return rc;
 }
 
 int bec_time_stage(bec_grid g, const bec_params* pp, const void* d_phi, int which, int reps, double* avg_ms) {

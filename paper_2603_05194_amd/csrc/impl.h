@@ -74,6 +74,12 @@ struct Grid {
     // passes that do not depend on each other run as parallel branches of the iteration
     hipStream_t aux = nullptr;
     hipEvent_t ev[kBranchEvents] = {};
+    // the solve uses the paper's step rule ||phi_{n+1} - phi_n||_inf <= tol (FP64 iterations
+    // compute the step's sums only then)
+    bool step_rule = false;
+    // launch-shape variant of the register kernels per launch site (0: default; see
+    // bec_autotune_kernels); lengths without variants ignore it
+    int variant[BEC_NSITES] = {};
 };
 
 // Event pool of an in-iteration profile: pairs are handed out in launch order and harvested
@@ -122,5 +128,6 @@ void launch_interp(Grid& src, Grid& dst, const void* in, int in_fp32, void* out,
 void launch_normalize(Grid& g, cpx<double>* phi);
 void launch_gauge(Grid& g, cpx<double>* phi);
 void launch_rotate(Grid& g, const cpx<double>* in, cpx<double>* out, double alpha);
+bool site_has_variants(const Grid& g, int site);   // launch-shape variants exist for this site
 
 }  // namespace bec

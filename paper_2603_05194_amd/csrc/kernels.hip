@@ -95,12 +95,27 @@ __device__ __forceinline__ double trap_at(const PrecArgs& p, const double* g2, i
     return 0.5 * (g2[0] * x * x + g2[1] * y * y + g2[2] * z * z);
 }
 
-template <typename R, int N> struct RFK {
-    static constexpr int E = rf_points<R>(N);
-    using T = RF<R, N, E>;
+// Launch shape of the register line kernels. Variant V (chosen per launch site, see
+// bec_autotune_kernels) keeps the L lines per block, hence the tiles and partial-sum rows:
+//  bit 0: half the points per thread in blocks of twice the threads (power-of-two lengths with
+//         at least 16 points per thread);
+//  bit 1: whole complex values through LDS even where the split exchange would be used.
+template <typename R, int N, int V = 0> struct RFK {
+    static constexpr int E0 = rf_points<R>(N);
+    static constexpr bool HALF = (V & 1) != 0 && odd_part(N) == 1 && E0 >= 16;
+    static constexpr int E = HALF ? E0 / 2 : E0;
+    static constexpr int NT = kThreads * (E0 / E);
+    using T = RF<R, N, E, NT, (V & 2) != 0>;
     static constexpr int L = T::L;
-    static constexpr int NT = kThreads;
 };
+
+// The variant that V amounts to for length N (bits that change nothing are cleared).
+template <typename R, int N> constexpr int rf_variant(int v) {
+    const int e0 = rf_points<R>(N);
+    const bool half_ok = odd_part(N) == 1 && e0 >= 16;
+    const bool split_default = RF<R, N, e0>::SPLIT || RF<R, N, e0 / (half_ok ? 2 : 1), half_ok ? 2 * kThreads : kThreads>::SPLIT;
+    return (half_ok ? (v & 1) : 0) | (split_default ? (v & 2) : 0);
+}
 
 // Two-density Parseval pass: both spectra live in registers. For power-of-two lengths with at
 // least 16 points per thread it takes half of them in blocks of twice the threads: the same L
@@ -110,7 +125,7 @@ template <typename R, int N> struct RFK2 {
     static constexpr int E1 = rf_points<R>(N);
     static constexpr int E = (odd_part(N) > 1 || E1 < 16) ? E1 : E1 / 2;
     static constexpr int NT = kThreads * (E1 / E);
-    using T = RF<R, N, E, NT>;
+    using T = RF<R, N, E, NT, true>;   // whole complex values through LDS
     static constexpr int L = T::L;
     static_assert(L == RFK<R, N>::L, "same tiles as the line kernels");
 };
@@ -160,6 +175,10 @@ __device__ void apply_finish(DevState& S) {
     S.mass = h3 * r[9];
     S.mu = h3 * r[10];
     S.E = S.Ekin + S.Epot + S.Eint + S.Edip + S.Erot;
+    // what the next iteration of Algorithm 1 needs from these parts: the shift alpha
+    // (alpha_Lap = alpha_V, without the rotation term) and the energy-test slack
+    S.alpha = S.Ekin + S.Epot + 2.0 * S.Eint + fabs(2.0 * S.Edip);
+    S.tau_E = S.tau_ulps * S.eps_E * (fabs(S.Ekin) + fabs(S.Epot) + fabs(S.Eint) + fabs(S.Edip) + fabs(S.Erot));
 }
 
 __global__ void k_apply_finish(DevState* st, int nbatch) {
@@ -296,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_fin(const double* __restrict__ par
     if (threadIdx.x == 0) {
         DevState& S = st[b];
         if constexpr (CTL == FC_RES) ctl_res(S);
-        else if constexpr (CTL == FC_DIR) ctl_dir(S);
+        else if constexpr (CTL == FC_DIR) { ctl_res(S); ctl_dir(S); }
         else if constexpr (CTL == FC_STEP) ctl_step(S);
         else if constexpr (CTL == FC_POST) ctl_post(S);
         else if constexpr (CTL == FC_APPLY) apply_finish(S);

@@ -56,15 +56,15 @@ template <typename R> constexpr int rf_points(int N) {
     return e;
 }
 
-template <typename R, int N, int E, int NT = kThreads> struct RF {
+template <typename R, int N, int E, int NT = kThreads, bool NOSPLIT = false> struct RF {
     static constexpr int TPL = N / E;          // threads per line
     static constexpr int L = NT / TPL;         // lines per block of NT threads
     static constexpr int LD = N + 1;           // LDS line stride (odd: spreads banks)
     static constexpr size_t lds_bytes = (size_t)L * LD * sizeof(cpx<R>);
     // Line kernels whose complex tile exceeds 48 KB exchange one component at a time through a
     // real tile of half the size (two barriers more per stage), so that LDS admits twice the
-    // blocks per CU (FP64 N = 512: 64 KB -> 32 KB, four blocks instead of two).
-    static constexpr bool SPLIT = lds_bytes > 48 * 1024;
+    // blocks per CU (FP64 N = 512: 64 KB -> 32 KB, four blocks instead of two), unless NOSPLIT.
+    static constexpr bool SPLIT = !NOSPLIT && lds_bytes > 48 * 1024;
     static constexpr size_t lds_line_bytes = SPLIT ? (size_t)L * LD * sizeof(R) : lds_bytes;
 };
 
@@ -163,6 +163,26 @@ template <int N, int E, int DIR> __device__ __forceinline__ int rf_in_index(int 
     using P = RfPlan<N>;
     constexpr int RD = P::template radix<DIR>(0);
     return jb + (N / E) * (i / RD) + (i % RD) * (N / RD);
+}
+
+// Zero padding and cropping at compile time. In the entry layout of direction DIR, slot i holds
+// position jb + (N/E)(i/R) + (i%R)(N/R) with R the first radix and jb + (N/E)(i/R) < N/R, so
+// for even R the position lies in the first half of the line iff i % R < R/2; the same holds
+// for the exit layout with R the last radix. A transform whose input is zero beyond N/2 (or
+// whose output is needed only below N/2) can then drop those slots as compile-time zeros (dead
+// values), and the first (last) butterfly stage simplifies.
+template <int N, int E, int DIR> constexpr bool rf_in_low_half(int i) {
+    constexpr int RD = RfPlan<N>::template radix<DIR>(0);
+    return RD % 2 != 0 || i % RD < RD / 2;
+}
+template <int N, int E, int DIR> constexpr bool rf_out_low_half(int i) {
+    constexpr int RD = RfPlan<N>::template radix<DIR>(RfPlan<N>::ns - 1);
+    return RD % 2 != 0 || i % RD < RD / 2;
+}
+// true when the slot test above decides the half exactly (even first / last radix)
+template <int N, int DIR> constexpr bool rf_in_half_exact() { return RfPlan<N>::template radix<DIR>(0) % 2 == 0; }
+template <int N, int DIR> constexpr bool rf_out_half_exact() {
+    return RfPlan<N>::template radix<DIR>(RfPlan<N>::ns - 1) % 2 == 0;
 }
 
 // Index of register slot i for the exit layout of direction DIR.

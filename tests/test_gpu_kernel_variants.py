@@ -1,0 +1,63 @@
+"""Launch-shape variants of the register kernels (bec_set_kernel_variants, bec_autotune_kernels):
+fields are bit for bit those of the default shape, sums agree to rounding, and a short solve
+under the tuner's choice tracks the default one; the oracle checks the apply."""
+import numpy as np
+import pytest
+
+import bec_inputs as bi
+import paper_2603_05194_amd as bec
+from oracle.energy import Model
+from tests.gpu_util import dev, host, params_of, rel_max, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+# 256-point padded y lines (128-wide grid, no variants) and 512-point padded x lines (variants)
+GRIDS = [("pancake_256", (256, 128, 16)), ("cigar_128", (160, 160, 32))]
+
+
+@pytest.mark.parametrize("name,n", GRIDS)
+@pytest.mark.parametrize("prec", [bec.BEC_FP64, bec.BEC_FP32])
+def test_variants_leave_fields_bit_identical(name, n, prec):
+    torch = torch_mod()
+    w = bi.WORKLOADS[name]
+    m = Model.from_workload(w, n=n)
+    p = params_of(m)
+    phi0 = bi.initial_guess(w, n)
+    g = bec.BecGrid(n, w.a, precision=prec)
+    g.ensure_symbol()
+    x = dev(phi0).to(g.cdtype)
+    ref_h, ref_mu, ref_Phi = g.apply_H(p, x, want_Phi=True)
+    if prec == bec.BEC_FP64:
+        assert rel_max(host(ref_h), m.H(phi0)) < 1e-12
+    for v in range(1, 4):
+        print(f"{name} {n} prec {prec} variant {v}", flush=True)
+        g.set_kernel_variants([v] * len(bec.SITES))
+        h, mu, Phi = g.apply_H(p, x, want_Phi=True)
+        torch.cuda.synchronize()
+        assert torch.equal(h, ref_h) and torch.equal(Phi, ref_Phi), v
+        assert abs(mu.item() - ref_mu.item()) <= 1e-13 * abs(ref_mu.item())
+
+
+def test_tuned_solve_tracks_default():
+    torch = torch_mod()
+    w = bi.WORKLOADS["pancake_256"]
+    n = (128, 128, 32)
+    m = Model.from_workload(w, n=n)
+    p = params_of(m)
+    phi0 = bi.initial_guess(w, n)
+    g = bec.BecGrid(n, w.a)
+    g.ensure_symbol()
+    o = bec.bec_pcg_default_opts()
+    o.max_iter = 200
+    a = dev(phi0)
+    ra = g.pcg_solve(p, a, o)
+    chosen, times = g.autotune_kernels(p, dev(phi0), iters=5)
+    print(f"tuned variants {chosen}")
+    assert set(chosen) <= set(bec.SITES) and times
+    g.set_kernel_variants([3] * len(bec.SITES))      # every shape change that exists on this grid
+    b = dev(phi0)
+    rb = g.pcg_solve(p, b, o)
+    torch.cuda.synchronize()
+    assert ra.iters == rb.iters == 200
+    assert abs(ra.e.E - rb.e.E) < 1e-12 * abs(ra.e.E)
+    assert float((a - b).abs().max()) < 1e-9
