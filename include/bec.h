@@ -168,6 +168,19 @@ int bec_pcg_solve(bec_grid g, const bec_params* p, void* d_phi, const bec_pcg_op
  * (BEC_ENUMERIC over BEC_ENOTCONV over BEC_OK). */
 int bec_pcg_solve_batched(bec_grid g, const bec_params* p, void* d_phi, const bec_pcg_opts* opts,
                           bec_pcg_result* h_results);
+/* Algorithm 1 for several grids of different sizes in one call (parameter sweeps over uneven
+ * grids, e.g. the transverse resolution growing with Omega): grids[k] is a handle with its own
+ * box, grid, precision and batch, params[k] its `batch` parameter sets, d_phis[k] its
+ * [batch][Nx][Ny][Nz] complex128 guesses (overwritten with the results). Each grid runs on a
+ * private stream of its own; the host issues every grid's iterations up to its next check of
+ * the device states, then reads the grids in turn, so the grids' iterations run side by side on
+ * the GPU and finished grids drop out. The handles must be distinct and use distinct
+ * workspaces. h_results receives sum_k batch_k results in grid order. Each solve's result is the
+ * one bec_pcg_solve_batched gives on its grid alone, bit for bit. Returns the worst status as
+ * bec_pcg_solve_batched, or the first error. A project addition (no passage of the paper; the
+ * sweeps are those of Sec. 3, critical rotational frequency). Synchronises. */
+int bec_pcg_solve_ragged(bec_grid* grids, const bec_params* const* params, void* const* d_phis, int ngrids,
+                         const bec_pcg_opts* opts, bec_pcg_result* h_results);
 int bec_pcg_default_opts(bec_pcg_opts* opts);
 
 /* 3-D C2C FFT on the N grid (unnormalised; dir = -1 forward exp(-2 pi i jk/N), +1 inverse),

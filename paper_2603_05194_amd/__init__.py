@@ -91,6 +91,8 @@ _SIGS = {
     "bec_pcg_solve": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.POINTER(bec_pcg_opts),
                                 C.POINTER(bec_pcg_result)]),
     "bec_pcg_default_opts": (C.c_int, [C.POINTER(bec_pcg_opts)]),
+    "bec_pcg_solve_ragged": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
+                                       C.POINTER(bec_pcg_opts), C.POINTER(bec_pcg_result)]),
     "bec_fft3d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "bec_time_stage": (C.c_int, [C.c_void_p, C.POINTER(bec_params), C.c_void_p, C.c_int, C.c_int,
                                  C.POINTER(C.c_double)]),
@@ -240,6 +242,39 @@ def bec_pcg_solve_batched(h, params_array, d_phi, batch, opts=None):
                                       C.byref(opts) if opts is not None else None, res)
     _check(rc, "bec_pcg_solve_batched", ok=(BEC_OK, BEC_ENOTCONV, BEC_ENUMERIC))
     return list(res)
+
+
+def bec_pcg_solve_ragged(handles, params_arrays, d_phis, batches, opts=None):
+    """handles, params_arrays (ctypes bec_params arrays), device pointers and batch sizes per grid;
+    returns the results of every solve in grid order."""
+    k = len(handles)
+    hs = (C.c_void_p * k)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    ps = (C.c_void_p * k)(*[C.cast(a, C.c_void_p).value for a in params_arrays])
+    ds = (C.c_void_p * k)(*d_phis)
+    res = (bec_pcg_result * sum(batches))()
+    rc = _lib().bec_pcg_solve_ragged(hs, ps, ds, k, C.byref(opts) if opts is not None else None, res)
+    _check(rc, "bec_pcg_solve_ragged", ok=(BEC_OK, BEC_ENOTCONV, BEC_ENUMERIC))
+    return list(res)
+
+
+def pcg_solve_ragged(grids, params_lists, phis_list, opts=None):
+    """Algorithm 1 on several BecGrid objects of different sizes in one call (see
+    bec_pcg_solve_ragged). params_lists[k]: the grid's bec_params list; phis_list[k]: its
+    contiguous complex128 [batch, Nx, Ny, Nz] tensor (overwritten). Returns one result list per grid."""
+    arrays = []
+    for g, pl, ph in zip(grids, params_lists, phis_list):
+        assert len(pl) == g.batch and ph.is_contiguous() and ph.dtype == g.torch.complex128
+        assert tuple(ph.shape) == (g.batch,) + g.n
+        if any(p.lambda_ != 0.0 for p in pl):
+            g.ensure_symbol()
+        arrays.append((bec_params * g.batch)(*pl))
+    flat = bec_pcg_solve_ragged([g.handle for g in grids], arrays, [ph.data_ptr() for ph in phis_list],
+                                [g.batch for g in grids], opts)
+    out, k = [], 0
+    for g in grids:
+        out.append(flat[k:k + g.batch])
+        k += g.batch
+    return out
 
 
 def bec_fft3d(h, d_in, d_out, direction):

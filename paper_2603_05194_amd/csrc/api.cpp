@@ -347,167 +347,227 @@ void close_branches(Grid& g) {
 }
 
 // ------------------------------------------------------------------ PCG driver
-// Runs Algorithm 1 for every solve of the batch with all scalar decisions on the device. The
-// host enqueues iterations (eagerly for the first two, then as a captured two-iteration HIP
-// graph) on a private non-blocking stream and reads the device states every check_every
-// iterations; it stops when every solve is done. In the FP32 phase it also stops solves whose
-// ||r||_inf has not dropped below 0.9x its best for stall_window iterations.
-template <typename R>
-int pcg_phase(Grid& g, cpx<R>* phi, const bec_pcg_opts& o, bool stall_stop, std::vector<DevState>& hs) {
-    int rc;
-    launch_pcg_start<R>(g, phi);
-    if ((rc = check_launch(&g, "pcg start"))) return rc;
-    const int every = o.check_every;
-    long it = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<double> best(g.batch, 1e300);
-    std::vector<long> best_it(g.batch, 0);
-    std::vector<int> stop(g.batch, 0);
-    const char* prog = std::getenv("BEC_PROGRESS");
-    const double prog_every = prog ? std::atof(prog) : 0.0;
-    auto now = []() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
-    double last_print = prog_every > 0 ? now() : 0.0;
-    for (;;) {
-        if (o.use_graph && it >= 2 && (it & 1) == 0) {
-            if (!exec) {
-                hipError_t e = hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) { rc = hip_fail(&g, e, "begin capture"); break; }
-                launch_pcg_iteration<R>(g, phi, 0);
-                launch_pcg_iteration<R>(g, phi, 1);
-                e = hipStreamEndCapture(g.stream, &graph);
-                if (e != hipSuccess) { rc = hip_fail(&g, e, "end capture"); break; }
-                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                if (e != hipSuccess) { rc = hip_fail(&g, e, "graph instantiate"); break; }
-            }
-            hipError_t e = hipGraphLaunch(exec, g.stream);
-            if (e != hipSuccess) { rc = hip_fail(&g, e, "graph launch"); break; }
-            it += 2;
+// Algorithm 1 for every solve of a batched grid with all scalar decisions on the device. The
+// host enqueues iterations (eagerly for the first two of a phase, then as a captured
+// two-iteration HIP graph) on a private non-blocking stream and reads the device states every
+// check_every iterations; a phase ends when every solve is done. On BEC_FP32 grids the FP32 bulk
+// phase also stops solves whose ||r||_inf has not dropped below 0.9x its best for stall_window
+// iterations, then the FP64 polish runs from the renormalised FP32 states.
+//
+// The run is resumable: issue() enqueues the iterations up to the next check and returns at
+// once; poll() waits for them, reads the states and moves on (stall stops, phase switch, end).
+// One grid alternates the two; several grids (bec_pcg_solve_ragged) issue in turn and then poll
+// in turn, so the grids' iterations run side by side on their own streams.
+class Solve {
+public:
+    Solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o) : g_(g), phi_(phi), o_(o) {}
+
+    int begin() {
+        user_ = g_.stream;
+        hipError_t e = hipStreamCreateWithFlags(&ps_, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev_, user_);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ps_, ev_, 0);
+        if (e != hipSuccess) return rc_ = hip_fail(&g_, e, "solve stream");
+        g_.stream = ps_;
+        g_.step_rule = o_.tol_step_inf > 0.0;
+        if (o_.branches && (rc_ = open_branches(g_))) return rc_;
+        const size_t NB = (size_t)g_.n[0] * g_.n[1] * g_.n[2] * g_.batch;
+        CtlOpts co;
+        co.tol_res = o_.tol_res_inf; co.tol_step = o_.tol_step_inf; co.t_default = o_.t_default;
+        co.tau_ulps = o_.tau_E_ulps; co.dbg_t = o_.debug_t; co.dbg_c2 = o_.debug_c2; co.max_iter = o_.max_iter;
+        co.max_halv = o_.max_halvings; co.dbg_flags = o_.debug_flags; co.fp32 = 0;
+        // clear the CG memory buffers and stop flags once (outside any captured graph)
+        e = hipMemsetAsync(g_.dstop, 0, g_.batch * sizeof(int), g_.stream);
+        if (e == hipSuccess) e = hipMemsetAsync(g_.f64.p, 0, NB * sizeof(cpx<double>), g_.stream);
+        if (e == hipSuccess) e = hipMemsetAsync(g_.f64.r1, 0, NB * sizeof(cpx<double>), g_.stream);
+        if (e != hipSuccess) return rc_ = hip_fail(&g_, e, "solve init");
+        fp32_ = g_.precision == BEC_FP32;
+        if (fp32_) {
+            // FP32 bulk phase: stop at ||r||_inf <= switch_res (times |mu| if relative) or when the
+            // residual stalls. The trial energies are FP64 polynomials of FP64 sums, so the energy
+            // test keeps its FP64 slack (an FP32-sized slack accepts energy increases and the
+            // phase never settles).
+            co.tol_res = o_.switch_relative ? o_.switch_res : std::max(o_.switch_res, o_.tol_res_inf);
+            co.tol_rel = o_.switch_relative ? 1 : 0;
+            launch_ctl_init(g_, co);
+            e = hipMemsetAsync(g_.f32.p, 0, NB * sizeof(cpx<float>), g_.stream);
+            if (e == hipSuccess) e = hipMemsetAsync(g_.f32.r1, 0, NB * sizeof(cpx<float>), g_.stream);
+            if (e != hipSuccess) return rc_ = hip_fail(&g_, e, "solve init");
+            launch_to_f32(g_, phi_, g_.f32.phi);
         } else {
-            launch_pcg_iteration<R>(g, phi, (int)(it & 1));
-            it += 1;
+            launch_ctl_init(g_, co);
         }
-        if ((rc = check_launch(&g, "pcg iteration"))) break;
-        if (it % every == 0 || it < 2) {
-            if ((rc = read_states(g, hs))) break;
-            bool all = true;
-            double rmin = 1e300, rmax = 0.0;
-            int ndone = 0;
-            bool new_stop = false;
-            for (int b = 0; b < g.batch; ++b) {
-                const DevState& S = hs[b];
-                if (S.done) { ++ndone; continue; }
-                all = false;
-                rmin = std::min(rmin, S.res_inf);
-                rmax = std::max(rmax, S.res_inf);
-                if (stall_stop) {
-                    if (S.res_inf < 0.9 * best[b]) { best[b] = S.res_inf; best_it[b] = S.iter; }
-                    else if (S.iter - best_it[b] >= o.stall_window && !stop[b]) { stop[b] = 1; new_stop = true; }
-                }
-            }
-            if (prog_every > 0 && now() - last_print >= prog_every) {
-                std::fprintf(stderr, "[bec] %s iter %d done %d/%d res %.3e..%.3e E0 %.15f\n", sizeof(R) == 4 ? "fp32" : "fp64",
-                             hs[0].iter, ndone, g.batch, rmin, rmax, hs[0].E);
-                std::fflush(stderr);
-                last_print = now();
-            }
-            if (all) break;
-            if (new_stop) {
-                hipError_t e = hipMemcpyAsync(g.dstop, stop.data(), g.batch * sizeof(int), hipMemcpyHostToDevice, g.stream);
-                if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
-                if (e != hipSuccess) { rc = hip_fail(&g, e, "stop flags"); break; }
-                launch_ctl_stop(g);
-            }
-        }
+        const char* prog = std::getenv("BEC_PROGRESS");
+        prog_every_ = prog ? std::atof(prog) : 0.0;
+        last_print_ = now();
+        return rc_ = start_phase();
     }
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
-    if (rc) return rc;
-    return read_states(g, hs);
-}
+
+    bool finished() const { return done_ || rc_ != BEC_OK; }
+    int rc() const { return rc_; }
+
+    int issue() {
+        if (finished()) return rc_;
+        return rc_ = fp32_ ? issue_t<float>(g_.f32.phi) : issue_t<double>(phi_);
+    }
+
+    int poll() {
+        if (finished()) return rc_;
+        if ((rc_ = read_states(g_, hs_))) return rc_;
+        bool all = true, new_stop = false;
+        double rmin = 1e300, rmax = 0.0;
+        int ndone = 0;
+        for (int b = 0; b < g_.batch; ++b) {
+            const DevState& S = hs_[b];
+            if (S.done) { ++ndone; continue; }
+            all = false;
+            rmin = std::min(rmin, S.res_inf);
+            rmax = std::max(rmax, S.res_inf);
+            if (fp32_) {
+                if (S.res_inf < 0.9 * best_[b]) { best_[b] = S.res_inf; best_it_[b] = S.iter; }
+                else if (S.iter - best_it_[b] >= o_.stall_window && !stop_[b]) { stop_[b] = 1; new_stop = true; }
+            }
+        }
+        if (prog_every_ > 0 && now() - last_print_ >= prog_every_) {
+            std::fprintf(stderr, "[bec] %dx%dx%d %s iter %d done %d/%d res %.3e..%.3e E0 %.15f\n", g_.n[0], g_.n[1],
+                         g_.n[2], fp32_ ? "fp32" : "fp64", hs_[0].iter, ndone, g_.batch, rmin, rmax, hs_[0].E);
+            std::fflush(stderr);
+            last_print_ = now();
+        }
+        if (all) {
+            drop_graph();
+            if (!fp32_) {
+                done_ = true;
+                return rc_;
+            }
+            // FP32 phase over: reopen the solves first (the normalisation kernels skip solves
+            // marked done), then the FP64 polish from the renormalised states
+            fp32_ = false;
+            launch_ctl_phase(g_, o_.tol_res_inf, o_.max_iter, o_.tau_E_ulps, 2.220446049250313e-16);
+            launch_to_f64_normalized(g_, g_.f32.phi, phi_);
+            if ((rc_ = check_launch(&g_, "phase switch"))) return rc_;
+            return rc_ = start_phase();
+        }
+        if (new_stop) {
+            hipError_t e = hipMemcpyAsync(g_.dstop, stop_.data(), g_.batch * sizeof(int), hipMemcpyHostToDevice, g_.stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(g_.stream);
+            if (e != hipSuccess) return rc_ = hip_fail(&g_, e, "stop flags");
+            launch_ctl_stop(g_);
+        }
+        return rc_;
+    }
+
+    // Tears down streams and graphs (also after an error) and fills `batch` results.
+    int finish(bec_pcg_result* res) {
+        drop_graph();
+        if (ps_) (void)hipStreamSynchronize(ps_);
+        close_branches(g_);
+        if (user_ || ps_) g_.stream = user_;
+        if (ev_) (void)hipEventDestroy(ev_);
+        if (ps_) (void)hipStreamDestroy(ps_);
+        ev_ = nullptr;
+        ps_ = nullptr;
+        if (rc_) return rc_;
+        if ((rc_ = read_states(g_, hs_))) return rc_;
+        int worst = BEC_OK;
+        for (int b = 0; b < g_.batch; ++b) {
+            const DevState& S = hs_[b];
+            bec_pcg_result& r = res[b];
+            r.status = S.status == 0 ? BEC_OK : S.status;
+            r.iters = S.iter;
+            r.halvings = S.halvings;
+            r.psd_resets = S.resets;
+            r.forced_accepts = S.forced;
+            r.fp32_iters = g_.precision == BEC_FP32 ? S.fp32_iters : 0;
+            r.res_inf = S.res_inf;
+            r.step_inf = g_.step_rule || g_.precision == BEC_FP32 ? S.step_inf : 0.0;
+            r.e.E = S.E; r.e.Ekin = S.Ekin; r.e.Epot = S.Epot; r.e.Eint = S.Eint;
+            r.e.Edip = S.Edip; r.e.Erot = S.Erot; r.e.mu = S.mu; r.e.mass = S.mass;
+            r.e.virial = 2 * S.Ekin - 2 * S.Epot + 3 * S.Eint + 3 * S.Edip;
+            if (r.status == BEC_ENUMERIC || (r.status == BEC_ENOTCONV && worst == BEC_OK)) worst = r.status;
+        }
+        return worst;
+    }
+
+private:
+    static double now() {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    }
+
+    int start_phase() {
+        it_ = 0;
+        best_.assign(g_.batch, 1e300);
+        best_it_.assign(g_.batch, 0);
+        stop_.assign(g_.batch, 0);
+        if (fp32_) launch_pcg_start<float>(g_, g_.f32.phi);
+        else launch_pcg_start<double>(g_, phi_);
+        return check_launch(&g_, "pcg start");
+    }
+
+    void drop_graph() {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+    }
+
+    // enqueue iterations up to the next check: after the first, then every check_every
+    template <typename R> int issue_t(cpx<R>* phi) {
+        const long every = o_.check_every;
+        do {
+            if (o_.use_graph && it_ >= 2 && (it_ & 1) == 0) {
+                if (!exec_) {
+                    hipError_t e = hipStreamBeginCapture(g_.stream, hipStreamCaptureModeThreadLocal);
+                    if (e != hipSuccess) return hip_fail(&g_, e, "begin capture");
+                    launch_pcg_iteration<R>(g_, phi, 0);
+                    launch_pcg_iteration<R>(g_, phi, 1);
+                    e = hipStreamEndCapture(g_.stream, &graph_);
+                    if (e != hipSuccess) return hip_fail(&g_, e, "end capture");
+                    e = hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0);
+                    if (e != hipSuccess) return hip_fail(&g_, e, "graph instantiate");
+                }
+                hipError_t e = hipGraphLaunch(exec_, g_.stream);
+                if (e != hipSuccess) return hip_fail(&g_, e, "graph launch");
+                it_ += 2;
+            } else {
+                launch_pcg_iteration<R>(g_, phi, (int)(it_ & 1));
+                it_ += 1;
+            }
+            int rc = check_launch(&g_, "pcg iteration");
+            if (rc) return rc;
+        } while (!(it_ % every == 0 || it_ < 2));
+        return BEC_OK;
+    }
+
+    Grid& g_;
+    cpx<double>* phi_;
+    bec_pcg_opts o_;
+    hipStream_t user_ = nullptr, ps_ = nullptr;
+    hipEvent_t ev_ = nullptr;
+    bool fp32_ = false, done_ = false;
+    int rc_ = BEC_OK;
+    long it_ = 0;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    std::vector<double> best_;
+    std::vector<long> best_it_;
+    std::vector<int> stop_;
+    std::vector<DevState> hs_;
+    double prog_every_ = 0.0, last_print_ = 0.0;
+};
 
 int pcg_solve(Grid& g, cpx<double>* phi, const bec_pcg_opts& o, bec_pcg_result* res) {
-    hipStream_t user = g.stream;
-    hipStream_t ps = nullptr;
-    hipEvent_t ev = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(ev, user);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ps, ev, 0);
-    if (e != hipSuccess) return hip_fail(&g, e, "solve stream");
-    g.stream = ps;
-    g.step_rule = o.tol_step_inf > 0.0;
-    int brc = o.branches ? open_branches(g) : BEC_OK;
-    if (brc) {
-        close_branches(g);
-        g.stream = user;
-        (void)hipEventDestroy(ev);
-        (void)hipStreamDestroy(ps);
-        return brc;
-    }
-    const size_t NB = (size_t)g.n[0] * g.n[1] * g.n[2] * g.batch;
-    CtlOpts co;
-    co.tol_res = o.tol_res_inf; co.tol_step = o.tol_step_inf; co.t_default = o.t_default; co.tau_ulps = o.tau_E_ulps;
-    co.dbg_t = o.debug_t; co.dbg_c2 = o.debug_c2; co.max_iter = o.max_iter; co.max_halv = o.max_halvings;
-    co.dbg_flags = o.debug_flags; co.fp32 = 0;
-    std::vector<DevState> hs;
-    int rc = BEC_OK;
-    // clear reductions, CG memory buffers and stop flags once (outside any captured graph)
-    e = hipMemsetAsync(g.dstop, 0, g.batch * sizeof(int), g.stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.f64.p, 0, NB * sizeof(cpx<double>), g.stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.f64.r1, 0, NB * sizeof(cpx<double>), g.stream);
-    if (e != hipSuccess) rc = hip_fail(&g, e, "solve init");
-    if (!rc && g.precision == BEC_FP32) {
-        // FP32 bulk phase: stop at ||r||_inf <= switch_res or when the residual stalls. The
-        // trial energies are FP64 polynomials of FP64 sums, so the energy test keeps its FP64
-        // slack (an FP32-sized slack accepts energy increases and the phase never settles).
-        co.tol_res = o.switch_relative ? o.switch_res : std::max(o.switch_res, o.tol_res_inf);
-        co.tol_rel = o.switch_relative ? 1 : 0;
-        co.fp32 = 0;
-        launch_ctl_init(g, co);
-        e = hipMemsetAsync(g.f32.p, 0, NB * sizeof(cpx<float>), g.stream);
-        if (e == hipSuccess) e = hipMemsetAsync(g.f32.r1, 0, NB * sizeof(cpx<float>), g.stream);
-        if (e != hipSuccess) rc = hip_fail(&g, e, "solve init");
-        if (!rc) {
-            launch_to_f32(g, phi, g.f32.phi);
-            rc = pcg_phase<float>(g, g.f32.phi, o, true, hs);
+    Solve s(g, phi, o);
+    if (!s.begin())
+        while (!s.finished()) {
+            if (s.issue()) break;
+            if (s.poll()) break;
         }
-        if (!rc) {
-            // reopen the solves first: the normalisation kernels skip solves marked done
-            launch_ctl_phase(g, o.tol_res_inf, o.max_iter, o.tau_E_ulps, 2.220446049250313e-16);
-            launch_to_f64_normalized(g, g.f32.phi, phi);
-            rc = check_launch(&g, "phase switch");
-        }
-        if (!rc) rc = pcg_phase<double>(g, phi, o, false, hs);
-    } else if (!rc) {
-        launch_ctl_init(g, co);
-        rc = pcg_phase<double>(g, phi, o, false, hs);
-    }
-    (void)hipStreamSynchronize(ps);
-    close_branches(g);
-    g.stream = user;
-    (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(ps);
-    if (rc) return rc;
-    int worst = BEC_OK;
-    for (int b = 0; b < g.batch; ++b) {
-        const DevState& S = hs[b];
-        bec_pcg_result& r = res[b];
-        r.status = S.status == 0 ? BEC_OK : S.status;
-        r.iters = S.iter;
-        r.halvings = S.halvings;
-        r.psd_resets = S.resets;
-        r.forced_accepts = S.forced;
-        r.fp32_iters = g.precision == BEC_FP32 ? S.fp32_iters : 0;
-        r.res_inf = S.res_inf;
-        r.step_inf = g.step_rule || g.precision == BEC_FP32 ? S.step_inf : 0.0;
-        r.e.E = S.E; r.e.Ekin = S.Ekin; r.e.Epot = S.Epot; r.e.Eint = S.Eint;
-        r.e.Edip = S.Edip; r.e.Erot = S.Erot; r.e.mu = S.mu; r.e.mass = S.mass;
-        r.e.virial = 2 * S.Ekin - 2 * S.Epot + 3 * S.Eint + 3 * S.Edip;
-        if (r.status == BEC_ENUMERIC || (r.status == BEC_ENOTCONV && worst == BEC_OK)) worst = r.status;
-    }
-    if (worst != BEC_OK) g_last_error = bec_status_string(worst);
-    return worst;
+    const int rc = s.finish(res);
+    if (rc != BEC_OK && rc != BEC_ENOTCONV && rc != BEC_ENUMERIC) return rc;
+    if (rc != BEC_OK) g_last_error = bec_status_string(rc);
+    return rc;
 }
 
 // Iterations of Algorithm 1 with every launch timed by its own events (see bec_pcg_profile).
@@ -834,6 +894,56 @@ int bec_pcg_solve_batched(bec_grid g, const bec_params* pp, void* d_phi, const b
 
 int bec_pcg_solve(bec_grid g, const bec_params* pp, void* d_phi, const bec_pcg_opts* opts, bec_pcg_result* res) {
     return bec_pcg_solve_batched(g, pp, d_phi, opts, res);
+}
+
+int bec_pcg_solve_ragged(bec_grid* grids, const bec_params* const* pp, void* const* d_phis, int ngrids,
+                         const bec_pcg_opts* opts, bec_pcg_result* res) {
+    if (!grids || !pp || !d_phis || !res) return fail(BEC_EINVAL, "NULL pointer");
+    if (ngrids < 1 || ngrids > 64) return fail(BEC_EINVAL, "ngrids must be in [1, 64]");
+    bec_pcg_opts o;
+    if (opts) o = *opts; else bec_pcg_default_opts(&o);
+    if (!(o.tol_res_inf >= 0.0) || o.max_iter < 0 || o.max_halvings < 0 || o.check_every < 1)
+        return fail(BEC_EINVAL, "bad options");
+    int rc;
+    for (int k = 0; k < ngrids; ++k) {
+        if ((rc = check_grid(grids[k]))) return rc;
+        if (!d_phis[k] || !pp[k]) return fail(BEC_EINVAL, "NULL field or parameter array");
+        for (int j = 0; j < k; ++j)
+            if (grids[j] == grids[k]) return fail(BEC_EINVAL, "a grid handle appears twice");
+    }
+    for (int k = 0; k < ngrids; ++k)
+        if ((rc = upload_params(*grids[k], pp[k]))) return rc;
+    std::vector<Solve> runs;
+    runs.reserve(ngrids);
+    for (int k = 0; k < ngrids; ++k) runs.emplace_back(*grids[k], (cpx<double>*)d_phis[k], o);
+    int err = BEC_OK;
+    for (int k = 0; k < ngrids && !err; ++k) err = runs[k].begin();
+    // issue every grid's iterations up to its next check, then wait for and read each grid in
+    // turn: while one grid is read, the others' iterations keep running on their streams
+    for (bool active = !err; active && !err;) {
+        active = false;
+        for (auto& r : runs)
+            if (!r.finished() && (err = r.issue())) break;
+        for (auto& r : runs) {
+            if (err) break;
+            if (!r.finished() && (err = r.poll())) break;
+            active = active || !r.finished();
+        }
+    }
+    int worst = BEC_OK;
+    long off = 0;
+    for (int k = 0; k < ngrids; ++k) {
+        const int w = runs[k].finish(res + off);
+        off += grids[k]->batch;
+        if (w != BEC_OK && w != BEC_ENOTCONV && w != BEC_ENUMERIC) {
+            if (!err) err = w;
+        } else if (w == BEC_ENUMERIC || (w == BEC_ENOTCONV && worst == BEC_OK)) {
+            worst = w;
+        }
+    }
+    if (err) return err;
+    if (worst != BEC_OK) g_last_error = bec_status_string(worst);
+    return worst;
 }
 
 }  // extern "C"

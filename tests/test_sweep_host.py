@@ -21,3 +21,11 @@ def test_critical_omega_rule():
     oc = critical_omega(rs)
     assert oc[1.0]["omega_c"] == 0.4 and oc[1.0]["bracket"] == [0.3, 0.4]
     assert oc[2.0]["omega_c"] is None
+
+
+def test_critical_omega_skips_unconverged_solves():
+    rs = [dict(lam=1.0, omega=0.1, Lz=0.0, status=0), dict(lam=1.0, omega=0.2, Lz=0.9, status=-4),
+          dict(lam=1.0, omega=0.3, Lz=1.0, status=0)]
+    oc = critical_omega(rs)
+    assert oc[1.0]["omega_c"] == 0.3 and oc[1.0]["bracket"] == [0.1, 0.3]
+    assert oc[1.0]["not_converged"] == [0.2]
