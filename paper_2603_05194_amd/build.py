@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libbec.so")
-SOURCES = ["kernels.hip", "api.cpp", "mlp.hip"]
+SOURCES = ["kernels.hip", "kernels_f32.hip", "api.cpp", "mlp.hip"]
 ARCH = os.environ.get("BEC_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [

@@ -2,6 +2,16 @@
 #pragma once
 #include "common.h"
 
+// kernels.hip is compiled twice so that the two halves build in parallel: once for the FP64
+// instantiations and everything shared, once (kernels_f32.hip, BEC_UNIT_F32) for the FP32
+// instantiations alone. In the FP32 unit the non-template kernels get internal linkage
+// (BEC_SHARED) and the non-template host functions are left out.
+#ifdef BEC_UNIT_F32
+#define BEC_SHARED static
+#else
+#define BEC_SHARED
+#endif
+
 namespace bec {
 
 // Geometry of one line pass: lines run along `axis` of a C-order 3-D array.

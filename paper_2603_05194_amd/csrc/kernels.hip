@@ -136,7 +136,7 @@ template <typename R, int N> struct RFK2 {
 // ------------------------------------------------------------------ finalize + apply energies
 // One block per solve: sums partials[b][nb][nq] over blocks in a fixed order (max for slots in
 // maxmask) into st[b].red[row][q0 + q].
-__global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partials, long part_stride, int nb,
+BEC_SHARED __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partials, long part_stride, int nb,
                                                        int nq, unsigned maxmask, DevState* __restrict__ st, int row,
                                                        int q0) {
     const int b = blockIdx.x;
@@ -181,7 +181,7 @@ __device__ void apply_finish(DevState& S) {
     S.tau_E = S.tau_ulps * S.eps_E * (fabs(S.Ekin) + fabs(S.Epot) + fabs(S.Eint) + fabs(S.Edip) + fabs(S.Erot));
 }
 
-__global__ void k_apply_finish(DevState* st, int nbatch) {
+BEC_SHARED __global__ void k_apply_finish(DevState* st, int nbatch) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbatch) return;
     apply_finish(st[b]);
@@ -191,7 +191,7 @@ __global__ void k_apply_finish(DevState* st, int nbatch) {
 // Per-axis tables T[m][k] = I(s_m; nu_k, b) = int_{-b}^{b} exp(-s^2 y^2) cos(nu y) dy,
 // nu_k = pi k / (2a) for k = 0..N (octant of the padded axis), b = 2a; closed form when s b > 6.5,
 // else Gauss-Legendre with the nodes/weights given for [-b, b].
-__global__ void k_sym_tables(const double* __restrict__ s_nodes, int ms, int nk, double nu_step, double b,
+BEC_SHARED __global__ void k_sym_tables(const double* __restrict__ s_nodes, int ms, int nk, double nu_step, double b,
                              const double* __restrict__ gy, const double* __restrict__ gw, int nq,
                              double* __restrict__ T) {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,7 +219,7 @@ __global__ void k_sym_tables(const double* __restrict__ s_nodes, int ms, int nk,
 // U = sum_m c_m Tx[m][kx] Ty[m][ky] Tz[m][kz] (compensated summation over m), stored in the
 // working layout [ky][kz][kx] (kx fastest): the x passes then read, for each of their columns
 // (ky, kz), one contiguous row over kx.
-__global__ void k_sym_contract(const double* __restrict__ c, int ms, const double* __restrict__ Tx,
+BEC_SHARED __global__ void k_sym_contract(const double* __restrict__ c, int ms, const double* __restrict__ Tx,
                                const double* __restrict__ Ty, const double* __restrict__ Tz, int nkx, int nky, int nkz,
                                double* __restrict__ U) {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -239,7 +239,7 @@ __global__ void k_sym_contract(const double* __restrict__ c, int ms, const doubl
 }
 
 // working layout [ky][kz][kx] -> octant layout [kx][ky][kz] (the documented output)
-__global__ void k_sym_to_octant(const double* __restrict__ U, int nkx, int nky, int nkz, double* __restrict__ out) {
+BEC_SHARED __global__ void k_sym_to_octant(const double* __restrict__ U, int nkx, int nky, int nkz, double* __restrict__ out) {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long tot = (long)nkx * nky * nkz;
     if (id >= tot) return;
