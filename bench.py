@@ -113,10 +113,11 @@ def kernel_src_hash():
     return m.hexdigest()[:16]
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, warm_iters=2, timed_iters=20, applies=5):
     """The CPU oracle on the host cores, a bounded sample of the same workload: the symbol (timed,
-    excluded), two H applies (median) and the oracle's Algorithm 1 for 1 and for 2 iterations from
-    the same guess; s/iteration is the difference, so set-up and final energies cancel."""
+    excluded), the median of `applies` H applies, and the oracle's Algorithm 1 from the seed-0
+    guess for warm_iters + timed_iters iterations, each iteration timed on its own; s/iteration is
+    the median of the timed ones (the first warm_iters are warm-up)."""
     import numpy as np
     import bec_inputs as bi
     from oracle import spectral, symbol
@@ -129,16 +130,14 @@ def cpu_baseline(w):
     m = Model.from_workload(w, uhat_full=uh)
     phi0 = bi.initial_guess(w)
     ta = []
-    for _ in range(2):
+    for _ in range(applies):
         t0 = time.perf_counter()
         m.H(phi0)
         ta.append(time.perf_counter() - t0)
-    t0 = time.perf_counter()
-    pcg(m, phi0, max_iter=1)
-    t1 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    pcg(m, phi0, max_iter=2)
-    t2 = time.perf_counter() - t0
+    stamps = []
+    t_start = time.perf_counter()
+    pcg(m, phi0, tol_res=0.0, max_iter=warm_iters + timed_iters, on_iter=lambda n: stamps.append(time.perf_counter()))
+    per = np.diff(np.array([t_start] + stamps))[warm_iters:]
     cpu = platform.processor() or ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -147,7 +146,8 @@ def cpu_baseline(w):
                 break
     except OSError:
         pass
-    return {"cores": spectral.WORKERS, "s_per_iter": t2 - t1, "s_per_apply": float(np.median(ta)),
+    return {"cores": spectral.WORKERS, "s_per_iter": float(np.median(per)), "s_per_apply": float(np.median(ta)),
+            "iters_timed": int(per.size), "warmup_iters": warm_iters, "applies_timed": applies,
             "symbol_s": t_sym, "cpu_model": cpu, "numpy": np.__version__}
 
 
@@ -155,10 +155,11 @@ def cpu_line(c, gpu_iters):
     """The cpu_baseline object: oracle s/iteration times the GPU's FP64 iteration count."""
     return {"value": c["s_per_iter"] * gpu_iters, "unit": "s", "cores": c["cores"], "kind": "oracle",
             "sample": f"oracle (FP64 NumPy/SciPy FFT, {c['cores']} threads) on the same workload: Algorithm 1 "
-                      f"for 1 and for 2 iterations from the seed-0 guess, s/iteration = the difference = "
-                      f"{c['s_per_iter']:.2f} s, times the GPU FP64 iteration count {gpu_iters} = extrapolated "
-                      f"time to ground state; H apply {c['s_per_apply']:.2f} s; symbol {c['symbol_s']:.1f} s "
-                      f"excluded", "extrapolated": True, **c}
+                      f"from the seed-0 guess, {c['warmup_iters']} warm-up iterations, then the median of "
+                      f"{c['iters_timed']} timed iterations = {c['s_per_iter']:.2f} s/iteration, times the GPU FP64 "
+                      f"iteration count {gpu_iters} = extrapolated time to ground state; H apply (median of "
+                      f"{c['applies_timed']}) {c['s_per_apply']:.2f} s; symbol {c['symbol_s']:.1f} s excluded",
+            "extrapolated": True, **c}
 
 
 def main():

@@ -77,8 +77,9 @@ def shift_alpha(model, phi, Phi):
 
 
 def pcg(model, phi0, tol_res=1e-8, tol_step=0.0, max_iter=20000, max_halvings=30,
-        t_default=0.3, tau_ulps=64.0, trace=False, debug=None):
-    """Run Algorithm 1 from phi0 (normalised). `debug` may hold:
+        t_default=0.3, tau_ulps=64.0, trace=False, debug=None, on_iter=None):
+    """Run Algorithm 1 from phi0 (normalised). `on_iter(n)`, if given, is called after each
+    completed iteration (timing only; it sees no state). `debug` may hold:
     'force_t' (first trial step every iteration), 'force_c2' (override c2),
     'nan_at' (iteration at which a NaN is injected into the trial)."""
     debug = debug or {}
@@ -165,5 +166,7 @@ def pcg(model, phi0, tol_res=1e-8, tol_step=0.0, max_iter=20000, max_halvings=30
         restart = not accepted
         phi, E_n, terms = phi_t, E_t, terms_t
         n += 1
+        if on_iter is not None:
+            on_iter(n)
     e = model.energies(phi)
     return PCGResult(phi, status, n, halv_total, resets, forced, res, step_inf, e, log)
