@@ -264,13 +264,18 @@ int bec_pcg_profile(bec_grid g, const bec_params* p, void* d_phi, int iters, int
 /* Launch-shape variants of the register-resident FFT kernels, per launch site (BEC_SITE_*):
  * 0 is the default shape; bit 0 halves the points per thread in blocks of twice the threads;
  * bit 1 exchanges whole complex values through LDS where the default exchanges one component at
- * a time (larger LDS tile, fewer barriers). For the two-density Parseval pass bit 0 selects the
- * line kernels' shape instead of its own. Lines per block, tiles, radices and every butterfly
+ * a time (larger LDS tile, fewer barriers); bit 2 doubles the lines per block (blocks of twice
+ * the threads, twice the LDS) for the lengths 256 and 512. For the
+ * two-density Parseval pass bit 0 selects the line kernels' shape instead of its own (its two
+ * transforms then run one after the other; its default runs them side by side, each butterfly's
+ * twiddles formed once for both), and the other bits change nothing. Radices and every butterfly
  * stay the same, so fields are identical bit for bit under every variant; block sums group the
- * points by thread, so reductions change at rounding level. Variants exist for the power-of-two
- * lengths of at least 16 points per thread and for lengths whose default tile uses the split
- * exchange; other sites ignore the setting. A project addition (performance only, no passage of
- * the paper). Arrays hold BEC_NSITES entries. */
+ * points by thread and block, so reductions change at rounding level. Variants exist for the
+ * power-of-two lengths of at least 16 points per thread, for 256 and 512, and for lengths whose
+ * default tile uses the split exchange; other sites ignore the setting. Values are
+ * 0 .. BEC_KERNEL_VARIANTS-1. A project addition (performance only, no passage of the paper).
+ * Arrays hold BEC_NSITES entries. */
+#define BEC_KERNEL_VARIANTS 8
 int bec_set_kernel_variants(bec_grid g, const int32_t* variants);
 int bec_get_kernel_variants(bec_grid g, int32_t* variants);
 /* Times every variant on every launch site with `iters` event-timed iterations of Algorithm 1

@@ -21,6 +21,7 @@ BEC_FP64, BEC_FP32 = 0, 1
 SITES = ("control", "finish", "prec_z", "prec_y", "prec_x", "prec_zi", "dir_z", "y_fwd", "x_pars2", "p_lines",
          "retract", "atkm_z", "x_atkm", "y_inv", "atkm_zi", "h_z", "h_y", "h_x", "other")
 BEC_NSITES = len(SITES)
+BEC_KERNEL_VARIANTS = 8   # launch-shape variants per site, 0 .. 7 (include/bec.h)
 
 
 class bec_grid_desc(C.Structure):

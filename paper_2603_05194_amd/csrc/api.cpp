@@ -1006,6 +1006,7 @@ int bec_pcg_profile(bec_grid g, const bec_params* pp, void* d_phi, int iters, in
     return run_profile(g, d_phi, iters, flags, site_ms, site_launches);
 }
 
+static_assert(bec::kKernelVariants == BEC_KERNEL_VARIANTS, "variant count of the header and the kernels");
 int bec_set_kernel_variants(bec_grid g, const int32_t* variants) {
     int rc = check_grid(g);
     if (rc) return rc;

@@ -28,7 +28,7 @@ constexpr int kTileElems = 4096;      // complex elements held in LDS by one lin
 constexpr int kMaxStages = 12;
 constexpr int kMaxRed = 32;           // reduction slots per kernel
 constexpr int kRedBlocks = 1024;      // blocks of the grid-stride pointwise reductions
-constexpr int kKernelVariants = 4;    // launch-shape variants of the register line kernels
+constexpr int kKernelVariants = 8;    // launch-shape variants of the register kernels (BEC_KERNEL_VARIANTS)
 
 // Line lengths with register-resident FFT kernels: powers of two 32..1024 and 3 or 5 times a
 // power of two (48..384, 160, 320). Every other length runs on the runtime-length LDS kernels.

@@ -96,17 +96,22 @@ __device__ __forceinline__ double trap_at(const PrecArgs& p, const double* g2, i
 }
 
 // Launch shape of the register line kernels. Variant V (chosen per launch site, see
-// bec_autotune_kernels) keeps the L lines per block, hence the tiles and partial-sum rows:
+// bec_autotune_kernels); bits 0 and 1 keep the L lines per block, hence the tiles and partial-sum rows:
 //  bit 0: half the points per thread in blocks of twice the threads (power-of-two lengths with
 //         at least 16 points per thread);
 //  bit 1: whole complex values through LDS even where the split exchange would be used.
+//  bit 2: twice the lines per block in blocks of twice the threads (lengths 256 and 512; the
+//         LDS tile of 1024 would not fit): 256-byte column segments in FP64, half the tiles.
+template <typename R, int N> constexpr bool rf_wide_ok() { return odd_part(N) == 1 && N >= 256 && N <= 512; }
 template <typename R, int N, int V = 0> struct RFK {
     static constexpr int E0 = rf_points<R>(N);
     static constexpr bool HALF = (V & 1) != 0 && odd_part(N) == 1 && E0 >= 16;
+    static constexpr bool WIDE = (V & 4) != 0 && rf_wide_ok<R, N>();
     static constexpr int E = HALF ? E0 / 2 : E0;
-    static constexpr int NT = kThreads * (E0 / E);
+    static constexpr int NT = kThreads * (E0 / E) * (WIDE ? 2 : 1);
     using T = RF<R, N, E, NT, (V & 2) != 0>;
     static constexpr int L = T::L;
+    static_assert(T::lds_line_bytes <= 160 * 1024, "line tile beyond the LDS of a CU");
 };
 
 // The variant that V amounts to for length N (bits that change nothing are cleared).
@@ -114,7 +119,7 @@ template <typename R, int N> constexpr int rf_variant(int v) {
     const int e0 = rf_points<R>(N);
     const bool half_ok = odd_part(N) == 1 && e0 >= 16;
     const bool split_default = RF<R, N, e0>::SPLIT || RF<R, N, e0 / (half_ok ? 2 : 1), half_ok ? 2 * kThreads : kThreads>::SPLIT;
-    return (half_ok ? (v & 1) : 0) | (split_default ? (v & 2) : 0);
+    return (half_ok ? (v & 1) : 0) | (split_default ? (v & 2) : 0) | (rf_wide_ok<R, N>() ? (v & 4) : 0);
 }
 
 // Two-density Parseval pass: both spectra live in registers. For power-of-two lengths with at

@@ -151,6 +151,91 @@ __device__ __forceinline__ void rf_run(cpx<R> (&v)[E], LP* __restrict__ line, in
     }
 }
 
+// Twiddles of stage S for butterfly j: w[k] = w1^k, k = 1..RD-1, from one table read.
+template <typename R, int N, int E, int DIR, int S>
+__device__ __forceinline__ void rf_twiddles(cpx<R> (&w)[8], int j, const cpx<R>* __restrict__ tw) {
+    using P = RfPlan<N>;
+    constexpr int RD = P::template radix<DIR>(S);
+    constexpr int Ns = P::template span<DIR>(S);
+    const int jm = j % Ns;
+    w[1] = tw[jm * (N / (Ns * RD))];
+    if constexpr (DIR > 0) w[1] = conj(w[1]);
+    if constexpr (RD > 2) w[2] = cmul(w[1], w[1]);
+    if constexpr (RD > 3) w[3] = cmul(w[2], w[1]);
+    if constexpr (RD > 4) w[4] = cmul(w[2], w[2]);
+    if constexpr (RD > 5) {
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[3], w[3]);
+        w[7] = cmul(w[4], w[3]);
+    }
+}
+
+// One LDS exchange between stage S and S+1 of the register layout (whole complex values).
+template <typename R, int N, int E, int DIR, int S>
+__device__ __forceinline__ void rf_exchange_cpx(cpx<R> (&v)[E], cpx<R>* __restrict__ line, int jb) {
+    using P = RfPlan<N>;
+    constexpr int RD = P::template radix<DIR>(S);
+    constexpr int Ns = P::template span<DIR>(S);
+    constexpr int TPL = N / E;
+    constexpr int BPT = E / RD;
+    constexpr int RN = P::template radix<DIR>(S + 1);
+    constexpr int BN = E / RN;
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int j = jb + TPL * b;
+        const int jm = j % Ns;
+        cpx<R>* o = line + (j - jm) * RD + jm;
+#pragma unroll
+        for (int k = 0; k < RD; ++k) o[k * Ns] = v[b * RD + k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BN; ++b) {
+        const int j = jb + TPL * b;
+#pragma unroll
+        for (int k = 0; k < RN; ++k) v[b * RN + k] = line[j + k * (N / RN)];
+    }
+    __syncthreads();
+}
+
+// Two transforms of the same length and direction side by side (two fields on the same lines):
+// each butterfly's twiddles are formed once and serve both, and the two register sets go
+// through the LDS line one after the other at each stage boundary.
+template <typename R, int N, int E, int DIR, int S>
+__device__ __forceinline__ void rf_run2(cpx<R> (&v)[E], cpx<R> (&u)[E], cpx<R>* __restrict__ line, int jb,
+                                        const cpx<R>* __restrict__ tw) {
+    using P = RfPlan<N>;
+    constexpr int RD = P::template radix<DIR>(S);
+    constexpr int Ns = P::template span<DIR>(S);
+    constexpr int TPL = N / E;
+    constexpr int BPT = E / RD;
+    static_assert(E % RD == 0, "points per thread must be a multiple of every radix");
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        if constexpr (Ns > 1) {
+            cpx<R> w[8];
+            rf_twiddles<R, N, E, DIR, S>(w, jb + TPL * b, tw);
+#pragma unroll
+            for (int k = 1; k < RD; ++k) {
+                v[b * RD + k] = cmul(v[b * RD + k], w[k]);
+                u[b * RD + k] = cmul(u[b * RD + k], w[k]);
+            }
+        }
+        dft_small<RD, DIR>(&v[b * RD]);
+        dft_small<RD, DIR>(&u[b * RD]);
+    }
+    if constexpr (S + 1 < P::ns) {
+        rf_exchange_cpx<R, N, E, DIR, S>(v, line, jb);
+        rf_exchange_cpx<R, N, E, DIR, S>(u, line, jb);
+        rf_run2<R, N, E, DIR, S + 1>(v, u, line, jb, tw);
+    }
+}
+
+template <typename R, int N, int E, int DIR>
+__device__ __forceinline__ void rf_fft2(cpx<R> (&v)[E], cpx<R> (&u)[E], cpx<R>* line, int jb, const cpx<R>* tw) {
+    rf_run2<R, N, E, DIR, 0>(v, u, line, jb, tw);
+}
+
 // Full transform; `line` is this thread's line in LDS (lds + l * LD elements of type LP).
 template <typename R, int N, int E, int DIR, typename LP>
 __device__ __forceinline__ void rf_fft(cpx<R> (&v)[E], LP* line, int jb, const cpx<R>* tw) {

@@ -29,13 +29,40 @@ def test_variants_leave_fields_bit_identical(name, n, prec):
     ref_h, ref_mu, ref_Phi = g.apply_H(p, x, want_Phi=True)
     if prec == bec.BEC_FP64:
         assert rel_max(host(ref_h), m.H(phi0)) < 1e-12
-    for v in range(1, 4):
+    for v in range(1, bec.BEC_KERNEL_VARIANTS):
         print(f"{name} {n} prec {prec} variant {v}", flush=True)
         g.set_kernel_variants([v] * len(bec.SITES))
         h, mu, Phi = g.apply_H(p, x, want_Phi=True)
         torch.cuda.synchronize()
         assert torch.equal(h, ref_h) and torch.equal(Phi, ref_Phi), v
         assert abs(mu.item() - ref_mu.item()) <= 1e-13 * abs(ref_mu.item())
+
+
+@pytest.mark.parametrize("name,n", GRIDS)
+def test_variants_track_default_iterations(name, n):
+    """Every pass of Algorithm 1 under every variant (the Parseval pass and the wide tiles
+    included): the iterate after 12 FP64 iterations is the default's to rounding."""
+    torch = torch_mod()
+    w = bi.WORKLOADS[name]
+    m = Model.from_workload(w, n=n)
+    p = params_of(m)
+    phi0 = bi.initial_guess(w, n)
+    g = bec.BecGrid(n, w.a)
+    g.ensure_symbol()
+    o = bec.bec_pcg_default_opts()
+    o.max_iter = 12
+    o.tol_res_inf = 0.0
+    ref = dev(phi0)
+    r0 = g.pcg_solve(p, ref, o)
+    for v in range(1, bec.BEC_KERNEL_VARIANTS):
+        print(f"{name} {n} iterations, variant {v} on every site", flush=True)
+        g.set_kernel_variants([v] * len(bec.SITES))
+        x = dev(phi0)
+        r = g.pcg_solve(p, x, o)
+        torch.cuda.synchronize()
+        assert r.iters == r0.iters == 12
+        assert abs(r.e.E - r0.e.E) < 1e-13 * abs(r0.e.E), v
+        assert float((x - ref).abs().max()) < 1e-11, v
 
 
 def test_tuned_solve_tracks_default():
