@@ -559,6 +559,11 @@ class BecGrid:
                 self.set_kernel_variants(store[key]["variants"])
                 return dict(store[key]["variants"]), None
         self.ensure_symbol()
+        # the library reads and overwrites batch x N complex128 values here, on FP32 grids too
+        shapes = ((self.batch,) + self.n,) + ((self.n,) if self.batch == 1 else ())
+        if not (phi_scratch.is_contiguous() and phi_scratch.dtype == self.torch.complex128
+                and tuple(phi_scratch.shape) in shapes):
+            raise ValueError(f"phi_scratch must be a contiguous complex128 tensor of shape {shapes[-1]}")
         if self.batch > 1 or not isinstance(params, bec_params):
             params = (bec_params * self.batch)(*params)
         v, d, b = bec_autotune_kernels(self.handle, params, phi_scratch.data_ptr(), iters)

@@ -231,6 +231,48 @@ def evaluate(net, draws, n, precision=BEC_FP32, max_iter=200000, log=None):
     return rows
 
 
+def diagnose(net, draws, n, precision=BEC_FP32, max_iter=15000, log=None):
+    """Where the learned start gains or loses, for draws of one gamma_z band: Algorithm 1 from four
+    starts per draw, all in one batch: the plain guess, the network's guess, the network's modulus
+    with the plain guess's phase ("envelope"), and the plain modulus with the network's phase
+    ("phase"). The mixed starts are formed on the host and brought to unit mass there. Returns one
+    record per draw: iterations, status and final energy per start, and each final energy's
+    difference from the plain start's."""
+    import torch
+    assert all(gz_band(float(d[3])) == gz_band(float(draws[0][3])) for d in draws)
+    a = box_for(float(draws[0][3]))
+    h3 = 8.0 * a[0] * a[1] * a[2] / (n[0] * n[1] * n[2])
+    plain = [plain_guess(d, n) for d in draws]
+    learned = predict(net, draws, n).cpu().numpy()
+    starts, kinds = [], ("plain", "learned", "envelope", "phase")
+    for k in range(len(draws)):
+        pl, le = plain[k], learned[k]
+        env = np.abs(le) * np.exp(1j * np.angle(pl))
+        pha = np.abs(pl) * np.exp(1j * np.angle(le))
+        for f in (pl, le, env, pha):
+            starts.append(f / math.sqrt(h3 * float(np.sum(np.abs(f) ** 2))))
+    opts = bec_pcg_default_opts()
+    opts.max_iter = int(max_iter)
+    reps = [d for d in draws for _ in kinds]
+    g, _, res, t = solve_batch(reps, n, starts, precision, opts)
+    del g
+    torch.cuda.synchronize()
+    rows = []
+    for k, d in enumerate(draws):
+        r = {kind: res[4 * k + j] for j, kind in enumerate(kinds)}
+        e0 = r["plain"].e.E
+        rows.append(dict(draw=[float(v) for v in d], band=gz_band(float(d[3])),
+                         **{kind: dict(status=x.status, iters=x.iters, E=x.e.E, dE=x.e.E - e0)
+                            for kind, x in r.items()}))
+        if log:
+            log(f"diagnose draw {k}: " + "  ".join(f"{kind} {x.iters} it dE {x.e.E - e0:+.2e}"
+                                                   f"{'' if x.status == 0 else ' (st %d)' % x.status}"
+                                                   for kind, x in r.items()))
+    if log:
+        log(f"diagnose band {gz_band(float(draws[0][3]))}: {len(draws)} draws x 4 starts in {t:.1f}s")
+    return rows
+
+
 def summarize(rows, rel_tol=1e-10):
     """Gain of the learned guess: median iteration ratio, batch-time ratio, and the count of
     draws where it ends at a higher energy (a loss of the network) or a lower one."""
@@ -325,9 +367,24 @@ def main(argv=None):
                     help="also solve the held-out draws from plain and learned guesses on this grid")
     ap.add_argument("--drop", type=float, default=1e-2, help="drop draws with boundary |phi| above this x max")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--diagnose-bands", type=int, nargs="*", default=None,
+                    help="only run diagnose() on the held-out draws of these gamma_z bands at --eval-grid")
+    ap.add_argument("--diag-per-band", type=int, default=4)
     args = ap.parse_args(argv)
     if args.time_step:
         print(json.dumps(time_step(args.time_step)), flush=True)
+        return
+    if args.diagnose_bands is not None:
+        grid = tuple(args.eval_grid or (256, 256, 64))
+        log = lambda s: print(s, file=sys.stderr, flush=True)
+        net = load_default()
+        val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(100)]
+        out = []
+        for band in args.diagnose_bands:
+            ds = [d for d in val if gz_band(float(d[3])) == band][:args.diag_per_band]
+            if ds:
+                out += diagnose(net, ds, grid, max_iter=args.max_iter, log=log)
+        print(json.dumps(dict(diagnose=dict(grid=list(grid), max_iter=args.max_iter, rows=out))), flush=True)
         return
     if args.eval_only:
         grid = tuple(args.eval_grid or (256, 256, 64))

@@ -88,3 +88,18 @@ def test_tuned_solve_tracks_default():
     assert ra.iters == rb.iters == 200
     assert abs(ra.e.E - rb.e.E) < 1e-12 * abs(ra.e.E)
     assert float((a - b).abs().max()) < 1e-9
+
+
+def test_autotune_kernels_checks_the_scratch_field():
+    """The tuner reads and overwrites batch x N complex128 values also on FP32 grids: a field of
+    another type or shape is refused before anything runs."""
+    torch = torch_mod()
+    w = bi.WORKLOADS["small_32"]
+    n = (32, 32, 16)
+    m = Model.from_workload(w, n=n)
+    p = params_of(m)
+    g = bec.BecGrid(n, w.a, precision=bec.BEC_FP32, batch=2)
+    with pytest.raises(ValueError):
+        g.autotune_kernels([p, p], torch.zeros((2,) + n, dtype=torch.complex64, device="cuda"), iters=2)
+    with pytest.raises(ValueError):
+        g.autotune_kernels([p, p], torch.zeros(n, dtype=torch.complex128, device="cuda"), iters=2)
