@@ -197,10 +197,20 @@ def predict(net, draws, n):
     return fine
 
 
-def evaluate(net, draws, n, precision=BEC_FP32, max_iter=200000, log=None):
+def envelope_start(learned, plain, n, a):
+    """The network's modulus with the plain guess's phase, at unit mass (host arrays; h^3 from the
+    box half-widths a): the start that keeps the network's envelope but not its vortex layout."""
+    h3 = 8.0 * a[0] * a[1] * a[2] / (n[0] * n[1] * n[2])
+    f = np.abs(learned) * np.exp(1j * np.angle(plain))
+    return f / math.sqrt(h3 * float(np.sum(np.abs(f) ** 2)))
+
+
+def evaluate(net, draws, n, precision=BEC_FP32, max_iter=200000, log=None, start="network"):
     """Algorithm 1 from the plain guess (phi_d of the trap Gaussian) and from the network's
     guess, for every draw, batched per gamma_z band. Returns one record per draw with the
-    iterations, final energies and status of both runs, and the wall time of both batches."""
+    iterations, final energies and status of both runs, and the wall time of both batches.
+    start="envelope": the learned run starts from envelope_start (network modulus, plain phase);
+    forming it on the host is counted in the learned start's time."""
     import torch
     opts = bec_pcg_default_opts()
     opts.max_iter = int(max_iter)
@@ -214,8 +224,12 @@ def evaluate(net, draws, n, precision=BEC_FP32, max_iter=200000, log=None):
         tp = time.perf_counter()
         lg = predict(net, ds, n)
         torch.cuda.synchronize()
+        starts = list(lg.cpu().numpy())
+        if start == "envelope":
+            a = box_for(float(ds[0][3]))
+            starts = [envelope_start(f, pl, n, a) for f, pl in zip(starts, gs)]
         t_pred = time.perf_counter() - tp
-        g1, _, r1, t1 = solve_batch(ds, n, list(lg.cpu().numpy()), precision, opts)
+        g1, _, r1, t1 = solve_batch(ds, n, starts, precision, opts)
         t1 += t_pred            # the network and the interpolation belong to the learned start's time
         del g1
         for k, i in enumerate(idx):
@@ -247,10 +261,8 @@ def diagnose(net, draws, n, precision=BEC_FP32, max_iter=15000, log=None):
     starts, kinds = [], ("plain", "learned", "envelope", "phase")
     for k in range(len(draws)):
         pl, le = plain[k], learned[k]
-        env = np.abs(le) * np.exp(1j * np.angle(pl))
         pha = np.abs(pl) * np.exp(1j * np.angle(le))
-        for f in (pl, le, env, pha):
-            starts.append(f / math.sqrt(h3 * float(np.sum(np.abs(f) ** 2))))
+        starts += [pl, le, envelope_start(le, pl, n, a), pha / math.sqrt(h3 * float(np.sum(np.abs(pha) ** 2)))]
     opts = bec_pcg_default_opts()
     opts.max_iter = int(max_iter)
     reps = [d for d in draws for _ in kinds]
@@ -370,6 +382,8 @@ def main(argv=None):
     ap.add_argument("--diagnose-bands", type=int, nargs="*", default=None,
                     help="only run diagnose() on the held-out draws of these gamma_z bands at --eval-grid")
     ap.add_argument("--diag-per-band", type=int, default=4)
+    ap.add_argument("--start", choices=("network", "envelope"), default="network",
+                    help="learned start of --eval-only: the network's field, or its modulus with the plain phase")
     args = ap.parse_args(argv)
     if args.time_step:
         print(json.dumps(time_step(args.time_step)), flush=True)
@@ -390,9 +404,9 @@ def main(argv=None):
         grid = tuple(args.eval_grid or (256, 256, 64))
         log = lambda s: print(s, file=sys.stderr, flush=True)
         val = [bi.mlp_param_draw(10 ** 6 + s) for s in range(args.val_start, args.val_start + args.val)]
-        rows = evaluate(load_default(), val, grid, max_iter=args.max_iter, log=log)
-        print(json.dumps(dict(eval=dict(grid=list(grid), max_iter=args.max_iter, summary=summarize(rows),
-                                        rows=rows))), flush=True)
+        rows = evaluate(load_default(), val, grid, max_iter=args.max_iter, log=log, start=args.start)
+        print(json.dumps(dict(eval=dict(grid=list(grid), max_iter=args.max_iter, start=args.start,
+                                        summary=summarize(rows), rows=rows))), flush=True)
         return
     log = lambda s: print(s, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
