@@ -78,7 +78,7 @@ def site_bytes(site, n, csize, lam=True):
         "prec_z": 4 * c + Phi,             # read H phi, phi, Phi; write r, W
         "prec_y": 2 * c,                   # W in place
         "prec_x": 2 * c,
-        "prec_zi": 7 * c + Phi,            # read W, phi, Phi, r, r_prev, H phi, p_prev; write P r
+        "prec_zi": 6 * c + Phi,            # read W, phi, Phi, r_prev, H phi, p_prev; write P r (r is formed again)
         "dir_z": 4 * c + Phi + 2 * Z,      # read phi, P r, p_prev, Phi; write p, Z1, Z2
         "y_fwd": Z + Y,
         "x_pars2": 2 * Y + octant,
@@ -97,12 +97,12 @@ def site_bytes(site, n, csize, lam=True):
 # HBM bytes per launch and site from rocprofv3 FETCH_SIZE / WRITE_SIZE (FETCH_SIZE scaled by the
 # copy-kernel calibration factor 2.0, WRITE_SIZE by 1.0), taken with the kernel sources hashing to
 # MEASURED_TRAFFIC_SRC; the roofline's traffic is null once the sources have changed.
-MEASURED_TRAFFIC_SRC = "78cbcd91169de4df"
+MEASURED_TRAFFIC_SRC = "21f6b46673f896b9"
 MEASURED_TRAFFIC = {
-    "atkm_z": 136.4e6, "y_fwd": 214.1e6, "x_atkm": 355.4e6, "y_inv": 220.4e6,
-    "atkm_zi": 127.5e6, "h_z": 134.4e6, "h_y": 201.5e6, "h_x": 327.2e6,
-    "prec_z": 302.2e6, "prec_y": 134.3e6, "prec_x": 134.4e6, "prec_zi": 513.1e6,
-    "dir_z": 440.9e6, "x_pars2": 367.6e6, "p_lines": 67.3e6, "retract": 201.4e6,
+    "atkm_z": 136.4e6, "y_fwd": 214.1e6, "x_atkm": 355.2e6, "y_inv": 220.4e6,
+    "atkm_zi": 127.7e6, "h_z": 134.4e6, "h_y": 201.5e6, "h_x": 268.8e6,
+    "prec_z": 302.2e6, "prec_y": 134.3e6, "prec_x": 134.4e6, "prec_zi": 440.6e6,
+    "dir_z": 440.9e6, "x_pars2": 367.5e6, "p_lines": 67.3e6, "retract": 201.3e6,
 }
 
 
@@ -178,6 +178,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--with-mixed", action="store_true", help="also time mixed precision from the plain guess")
     ap.add_argument("--quick", action="store_true", help="reduced grid (for testing the script)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="every solve without the second stream (for kernel traces whose durations are each "
+                         "kernel's own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -215,6 +218,8 @@ def main():
     ob = bec.bec_pcg_default_opts()
     ob.tol_res_inf = 0.0          # fixed-length blocks
     ob.max_iter = args.block
+    if args.one_stream:
+        ob.branches = 0
     phi_b = guess(0)
     torch.cuda.synchronize()
     for i in range(args.warmup):
@@ -279,6 +284,8 @@ def main():
     reserve = 15.0
     cap = int(max(1000, it_per_s * (deadline - time.monotonic() - reserve)))
     opts.max_iter = min(cap, 2_000_000) if args.solve_iters is None else args.solve_iters
+    if args.one_stream:
+        opts.branches = 0
     phi = guess(0)
     torch.cuda.synchronize()
     log(f"full FP64 solve, iteration cap {opts.max_iter}")
