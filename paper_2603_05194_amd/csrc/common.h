@@ -23,6 +23,16 @@ template <int S, typename R> __host__ __device__ __forceinline__ cpx<R> mul_i(cp
     return S > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x);
 }
 
+// Streaming (nontemporal) store of a field value, for outputs that the pass right after does
+// not read: they then bypass the caches instead of displacing the inputs of the next pass. Used
+// where it measured faster (the padded y forward's output, the retraction, the preconditioned
+// residual, the direction, r and H phi); outputs that the next pass reads keep plain stores.
+template <typename R> __device__ __forceinline__ void st_stream(cpx<R>* p, cpx<R> v) {
+    typedef R V2 __attribute__((ext_vector_type(2)));
+    V2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<V2*>(p));
+}
+
 constexpr int kThreads = 256;         // threads per block of every field kernel
 constexpr int kTileElems = 4096;      // complex elements held in LDS by one line-FFT block
 constexpr int kMaxStages = 12;
