@@ -27,10 +27,19 @@ template <int S, typename R> __host__ __device__ __forceinline__ cpx<R> mul_i(cp
 // not read: they then bypass the caches instead of displacing the inputs of the next pass. Used
 // where it measured faster (the padded y forward's output, the retraction, the preconditioned
 // residual, the direction, r and H phi); outputs that the next pass reads keep plain stores.
+// Streaming loads likewise for inputs read once: the padded x passes' spectra (the symbol rows,
+// which the +ky and -ky columns share, stay cached) and the last preconditioner pass's W, r_prev
+// and p_prev.
 template <typename R> __device__ __forceinline__ void st_stream(cpx<R>* p, cpx<R> v) {
     typedef R V2 __attribute__((ext_vector_type(2)));
     V2 t = {v.x, v.y};
     __builtin_nontemporal_store(t, reinterpret_cast<V2*>(p));
+}
+
+template <typename R> __device__ __forceinline__ cpx<R> ld_stream(const cpx<R>* p) {
+    typedef R V2 __attribute__((ext_vector_type(2)));
+    const V2 t = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+    return mk<R>(t.x, t.y);
 }
 
 constexpr int kThreads = 256;         // threads per block of every field kernel
