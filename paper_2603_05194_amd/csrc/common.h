@@ -28,8 +28,8 @@ template <int S, typename R> __host__ __device__ __forceinline__ cpx<R> mul_i(cp
 // where it measured faster (the padded y forward's output, the retraction, the preconditioned
 // residual, the direction, r and H phi); outputs that the next pass reads keep plain stores.
 // Streaming loads likewise for inputs read once: the padded x passes' spectra (the symbol rows,
-// which the +ky and -ky columns share, stay cached) and the last preconditioner pass's W, r_prev
-// and p_prev.
+// which the +ky and -ky columns share, stay cached), the last preconditioner pass's W, r_prev
+// and p_prev, the direction pass's P r and p_prev, and the x operator's partial sum.
 template <typename R> __device__ __forceinline__ void st_stream(cpx<R>* p, cpx<R> v) {
     typedef R V2 __attribute__((ext_vector_type(2)));
     V2 t = {v.x, v.y};
