@@ -280,7 +280,8 @@ int bec_set_kernel_variants(bec_grid g, const int32_t* variants);
 int bec_get_kernel_variants(bec_grid g, int32_t* variants);
 /* Times every variant on every launch site with `iters` event-timed iterations of Algorithm 1
  * each (as bec_pcg_profile on one stream, from d_phi, which is overwritten), keeps per site that
- * has variants the fastest one if it beats the default by more than 2 %, leaves the choice on
+ * has variants the fastest one if it beats the default by more than 2 % (of variants that launch
+ * the same kernels at a site only the lowest counts), leaves the choice on
  * the grid and
  * returns it in variants_out; ms_default / ms_best receive the per-iteration milliseconds of
  * each site under the default and the chosen variant (all three nullable). Synchronises. */

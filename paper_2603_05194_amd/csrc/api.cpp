@@ -1045,7 +1045,7 @@ int bec_autotune_kernels(bec_grid g, const bec_params* pp, void* d_phi, int iter
         int best = 0;
         if (!rc && site_has_variants(*g, s))
             for (int v = 1; v < kKernelVariants; ++v)
-                if (ms[v][s] < 0.98 * ms[0][s] && ms[v][s] < ms[best][s]) best = v;
+                if (site_variant_distinct(*g, s, v) && ms[v][s] < 0.98 * ms[0][s] && ms[v][s] < ms[best][s]) best = v;
         g->variant[s] = best;
         if (variants_out) variants_out[s] = best;
         if (ms_default) ms_default[s] = rc ? 0.0 : ms[0][s] / iters;

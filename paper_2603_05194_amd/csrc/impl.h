@@ -129,5 +129,6 @@ void launch_normalize(Grid& g, cpx<double>* phi);
 void launch_gauge(Grid& g, cpx<double>* phi);
 void launch_rotate(Grid& g, const cpx<double>* in, cpx<double>* out, double alpha);
 bool site_has_variants(const Grid& g, int site);   // launch-shape variants exist for this site
+bool site_variant_distinct(const Grid& g, int site, int v);   // v launches kernels no u < v does
 
 }  // namespace bec

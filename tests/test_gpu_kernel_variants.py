@@ -81,6 +81,8 @@ def test_tuned_solve_tracks_default():
     chosen, times = g.autotune_kernels(p, dev(phi0), iters=5)
     print(f"tuned variants {chosen}")
     assert set(chosen) <= set(bec.SITES) and times
+    # the Parseval pass has one shape variant (bit 0); no other value can be chosen there
+    assert chosen.get("x_pars2", 0) in (0, 1)
     g.set_kernel_variants([3] * len(bec.SITES))      # every shape change that exists on this grid
     b = dev(phi0)
     rb = g.pcg_solve(p, b, o)
