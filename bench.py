@@ -10,7 +10,8 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--block B] [--budget S] [--
   from the previous block's iterate (the first block starts from the seed-0 random-phase guess);
   W untimed blocks, then K timed ones give ms_per_step and iterations/s. Inputs are resident in
   HBM before the timed region.
-* `value` is the time of one full FP64 solve from the seed-0 guess to ||H phi - mu phi||_inf <= 1e-8.
+* `value` is the time of one full FP64 solve from the seed-0 guess (--seed) to
+  ||H phi - mu phi||_inf <= 1e-8.
   Its iteration cap comes from the wall budget (--budget seconds from the start of the script,
   default 540) and the measured iteration rate, so the JSON line is always printed; a capped
   solve is reported as such (`solve.status`).
@@ -178,6 +179,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--with-mixed", action="store_true", help="also time mixed precision from the plain guess")
     ap.add_argument("--quick", action="store_true", help="reduced grid (for testing the script)")
+    ap.add_argument("--seed", type=int, default=0,
+                    help="random-phase guess of the full solve and of the learned starts (the timed blocks use seed 0)")
+    ap.add_argument("--learned-starts", default="envelope,network",
+                    help="comma-separated learned starts to run: envelope, network")
     ap.add_argument("--one-stream", action="store_true",
                     help="every solve without the second stream (for kernel traces whose durations are each "
                          "kernel's own)")
@@ -286,9 +291,9 @@ def main():
     opts.max_iter = min(cap, 2_000_000) if args.solve_iters is None else args.solve_iters
     if args.one_stream:
         opts.branches = 0
-    phi = guess(0)
+    phi = guess(args.seed)
     torch.cuda.synchronize()
-    log(f"full FP64 solve, iteration cap {opts.max_iter}")
+    log(f"full FP64 solve from the seed-{args.seed} guess, iteration cap {opts.max_iter}")
     t0 = time.perf_counter()
     ref = g.pcg_solve(p, phi, opts)
     torch.cuda.synchronize()
@@ -310,8 +315,8 @@ def main():
                          math.atan2(w.ndip[1], w.ndip[0])])
         gm = bec.BecGrid(n, w.a, precision=bec.BEC_FP32)
         gm.ensure_symbol()
-        g0 = bi.initial_guess(bi.Workload(**{**w.to_dict(), "seed": 0}))
-        for mode in ("envelope", "network"):
+        g0 = bi.initial_guess(bi.Workload(**{**w.to_dict(), "seed": args.seed}))
+        for mode in [m for m in ("envelope", "network") if m in args.learned_starts.split(",")]:
             left = deadline - time.monotonic()
             need = 0.45 * t_solve + 20.0
             if left < need:
@@ -379,9 +384,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pancake trap {n[0]}x{n[1]}x{n[2]} on [-16,16]^2x[-2,2], gamma=(1,1,20), "
                                f"beta=2000, lambda=600, n=(sin30,0,cos30), Omega=0.9, random-phase Gaussian guess "
-                               f"seed 0; value: FP64 PCG-ATKM to ||r||_inf<=1e-8; step: {args.block} FP64 PCG "
+                               f"seed {args.seed}; value: FP64 PCG-ATKM to ||r||_inf<=1e-8; step: {args.block} FP64 PCG "
                                f"iterations",
-                   "grid": list(n), "padded": [2 * v for v in n], "tol_res_inf": 1e-8, "block_iters": args.block},
+                   "grid": list(n), "padded": [2 * v for v in n], "tol_res_inf": 1e-8, "block_iters": args.block,
+                   "seed": args.seed},
         "solve": {"status": ref.status, "converged": converged, "iters": ref.iters, "res_inf": ref.res_inf,
                   "E": ref.e.E, "mu": ref.e.mu, "iter_cap": opts.max_iter,
                   "note": None if converged else "iteration cap from the wall budget reached: not a ground state"},
