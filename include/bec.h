@@ -52,7 +52,9 @@ enum {
     BEC_ESTALL = -6     /* reserved */
 };
 
-typedef enum { BEC_FP64 = 0, BEC_FP32 = 1 } bec_precision;
+/* BEC_MIXED is another name for BEC_FP32: a BEC_FP32 grid holds FP64 and FP32 fields and its
+ * solves run the FP32 bulk phase, then the FP64 polish. */
+typedef enum { BEC_FP64 = 0, BEC_FP32 = 1, BEC_MIXED = 1 } bec_precision;
 
 /* Box and grid (Sec. 2.1): N_a even, 4 <= N_a <= 2048, each N_a = 2^i 3^j 5^k. */
 typedef struct { int32_t n[3]; double a[3]; } bec_grid_desc;

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbec.so")
 
 BEC_OK, BEC_EINVAL, BEC_ENOMEM, BEC_EHIP, BEC_ENOTCONV, BEC_ENUMERIC, BEC_ESTALL = 0, -1, -2, -3, -4, -5, -6
 BEC_FP64, BEC_FP32 = 0, 1
+BEC_MIXED = BEC_FP32      # the same precision mode under the name the mixed-precision path goes by
 # launch sites of one PCG iteration (bec_pcg_profile), in the order of the BEC_SITE_* enum
 SITES = ("control", "finish", "prec_z", "prec_y", "prec_x", "prec_zi", "dir_z", "y_fwd", "x_pars2", "p_lines",
          "retract", "atkm_z", "x_atkm", "y_inv", "atkm_zi", "h_z", "h_y", "h_x", "other")
