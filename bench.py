@@ -84,7 +84,7 @@ def site_bytes(site, n, csize, lam=True):
         "y_fwd": Z + Y,
         "x_pars2": 2 * Y + octant,
         "p_lines": c,                      # read p (Parseval only)
-        "retract": 3 * c,                  # read phi, p; write phi
+        "retract": 3 * c + Z,              # retraction in the z R2C of |phi|^2: read phi, p; write phi, Z1
         "atkm_z": c + Z,                   # read phi; write Z1
         "x_atkm": 2 * Y + octant,          # Y1 in place + symbol
         "y_inv": Y + Z,

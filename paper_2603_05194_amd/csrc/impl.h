@@ -105,7 +105,8 @@ template <typename R> inline const Bat& bat(const Grid& g) { return sizeof(R) ==
 // launch wrappers (kernels.hip). Parameters are read on the device from DevState[b].
 template <typename R> void launch_fft3d(Grid& g, const cpx<R>* in, cpx<R>* out, int dir);
 template <typename R> void launch_atkm(Grid& g, const cpx<R>* phi, R* Phi);
-template <typename R> void launch_apply(Grid& g, const cpx<R>* phi, cpx<R>* hphi, R* Phi);
+// P_ret: the FP64 iteration's direction, for the retraction fused into the first ATKM pass
+template <typename R> void launch_apply(Grid& g, const cpx<R>* phi, cpx<R>* hphi, R* Phi, const cpx<R>* P_ret = nullptr);
 void launch_symbol(Grid& g, std::vector<double>& tables_host_scratch);
 void launch_symbol_out(Grid& g, double* out);   // octant layout [Nx+1][Ny+1][Nz+1]
 void launch_set_params(Grid& g);   // copies g.dparams[b] into st[b] (already uploaded)
