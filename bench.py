@@ -98,12 +98,12 @@ def site_bytes(site, n, csize, lam=True):
 # HBM bytes per launch and site from rocprofv3 FETCH_SIZE / WRITE_SIZE (FETCH_SIZE scaled by the
 # copy-kernel calibration factor 2.0, WRITE_SIZE by 1.0), taken with the kernel sources hashing to
 # MEASURED_TRAFFIC_SRC; the roofline's traffic is null once the sources have changed.
-MEASURED_TRAFFIC_SRC = "d4077efd4dda0dbf"
+MEASURED_TRAFFIC_SRC = "955e154b7ff25205"
 MEASURED_TRAFFIC = {
-    "atkm_z": 136.4e6, "y_fwd": 214.1e6, "x_atkm": 324.9e6, "y_inv": 220.4e6,
-    "atkm_zi": 126.3e6, "h_z": 134.4e6, "h_y": 201.5e6, "h_x": 268.8e6,
-    "prec_z": 302.2e6, "prec_y": 134.3e6, "prec_x": 134.4e6, "prec_zi": 436.5e6,
-    "dir_z": 440.9e6, "x_pars2": 337.4e6, "p_lines": 67.3e6, "retract": 201.3e6,
+    "atkm_z": 136.4e6, "y_fwd": 214.2e6, "x_atkm": 324.9e6, "y_inv": 220.4e6,
+    "atkm_zi": 126.8e6, "h_z": 134.4e6, "h_y": 201.6e6, "h_x": 268.8e6,
+    "prec_z": 302.2e6, "prec_y": 134.3e6, "prec_x": 134.4e6, "prec_zi": 436.6e6,
+    "dir_z": 440.9e6, "x_pars2": 337.5e6, "p_lines": 67.3e6, "retract": 270.6e6,
 }
 
 
