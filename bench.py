@@ -188,7 +188,7 @@ def main():
                          "kernel's own)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs a solve on one GPU; --gpus must be 1"}))
         sys.exit(2)
     deadline = T_START + args.budget
 
